@@ -1,0 +1,463 @@
+/*
+ * mpdata_ref.c -- plain, slow CPU FP64 oracle of one MPDATA step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the GPU path includes, links or calls
+ * this file; it shares no code, header, table or helper with that path.  Only
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark load
+ * it.  It is built with -O2 -ffp-contract=off (no FMA contraction, no
+ * fast-math), and every expression is evaluated exactly as parenthesised.
+ * It is neither tiled nor fused: every stage is a full-array loop, in the
+ * order of the scheme.  The only parallelism is an OpenMP loop over levels.
+ *
+ * Stages and where they come from:
+ *   C1 donor-cell flux        paper, Section 5, Listings 4-5 (edge flux with
+ *                             max(0,v) / min(0,v) weights) and Listings 6-7
+ *                             (the same along the vertical, boundary factor 0)
+ *   C2 divergence and update  paper, Section 5, Listing 8 (flux, vertical
+ *                             flux, flux divergence over the cell's metric
+ *                             volume, solution update)
+ *   C3 antidiffusive velocity MPDATA literature (the paper refers the rest
+ *   C4 limiter bounds, beta   of the scheme to another deliverable): the
+ *   C5 limited velocities     antidiffusive pseudo-velocity of Smolarkiewicz
+ *   C6 corrective pass        (1984) in the metric form of Smolarkiewicz &
+ *                             Margolin (1998), limited as in Smolarkiewicz &
+ *                             Grabowski (1990)
+ *   C7 mass                   sum(G psi), Neumaier compensated summation
+ */
+#include "mpdata_ref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define DEFAULT_EPS 1e-15
+
+/* ------------------------------------------------------------------ */
+/* Index helpers                                                      */
+/* ------------------------------------------------------------------ */
+
+static int64_t lin(const ref_problem* p, int i, int j, int k)
+{
+    return ((int64_t)k * p->ny + j) * p->nx + i;
+}
+
+static int extent(const ref_problem* p, int axis)
+{
+    return axis == 0 ? p->nx : (axis == 1 ? p->ny : p->nz);
+}
+
+/* Cell index along an axis with the halo rule: periodic wraps, closed clamps
+ * (a zero-gradient halo). */
+static int cell_index(const ref_problem* p, int axis, int i)
+{
+    int n = extent(p, axis);
+    if (p->bc[axis] == REF_PERIODIC) return ((i % n) + n) % n;
+    if (i < 0) return 0;
+    if (i > n - 1) return n - 1;
+    return i;
+}
+
+/* Cell value a(c) with the halo rule applied on every axis. */
+static double cellv(const ref_problem* p, const double* a, const int c[3])
+{
+    int i = cell_index(p, 0, c[0]);
+    int j = cell_index(p, 1, c[1]);
+    int k = cell_index(p, 2, c[2]);
+    return a[lin(p, i, j, k)];
+}
+
+/* Face value on axis `axis`: face (c[axis] + 1/2), the other two coordinates
+ * being cell coordinates (halo rule applied).  On a closed axis the faces
+ * -1/2 and n-1/2 (and anything beyond) carry 0; on a periodic axis the face
+ * index wraps. */
+static double facev(const ref_problem* p, const double* a, int axis, const int c[3])
+{
+    int d[3];
+    for (int b = 0; b < 3; ++b)
+        d[b] = (b == axis) ? c[b] : cell_index(p, b, c[b]);
+    int n = extent(p, axis);
+    if (p->bc[axis] == REF_CLOSED) {
+        if (d[axis] <= -1 || d[axis] >= n - 1) return 0.0;
+    } else {
+        d[axis] = ((d[axis] % n) + n) % n;
+    }
+    return a[lin(p, d[0], d[1], d[2])];
+}
+
+/* Is face (c[axis] + 1/2) with 0 <= c[axis] < n a closed-boundary face? */
+static int is_wall_face(const ref_problem* p, int axis, int ia)
+{
+    return p->bc[axis] == REF_CLOSED && ia == extent(p, axis) - 1;
+}
+
+static double pos(double c) { return c > 0.0 ? c : 0.0; }   /* [c]+ */
+static double neg(double c) { return c < 0.0 ? c : 0.0; }   /* [c]- */
+static double dmin(double a, double b) { return a < b ? a : b; }
+static double dmax(double a, double b) { return a > b ? a : b; }
+
+static int valid(const ref_problem* p)
+{
+    if (!p) return 0;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (p->bc[a] != REF_PERIODIC && p->bc[a] != REF_CLOSED) return 0;
+    if (p->iters < 1) return 0;
+    if (p->limiter != 0 && p->limiter != 1) return 0;
+    if (p->eps < 0.0) return 0;
+    return 1;
+}
+
+static double eps_of(const ref_problem* p)
+{
+    return p->eps > 0.0 ? p->eps : DEFAULT_EPS;
+}
+
+static int64_t ncells(const ref_problem* p)
+{
+    return (int64_t)p->nx * p->ny * p->nz;
+}
+
+/* ------------------------------------------------------------------ */
+/* C1-C2: donor-cell pass                                             */
+/* ------------------------------------------------------------------ */
+
+/* C1: upwind flux through a face whose normal points from the cell with
+ * value pl to the cell with value pr (paper, Listing 5 and Listing 7). */
+static double donor(double pl, double pr, double c)
+{
+    return (pos(c) * pl) + (neg(c) * pr);
+}
+
+int ref_donor(const ref_problem* p, const double* phi, const double* u,
+              const double* v, const double* w, const double* g, double* out)
+{
+    if (!valid(p) || !phi || !u || !v || !w || !g || !out) return -1;
+    const double* vel[3] = {u, v, w};
+    int64_t n = ncells(p);
+    double* flx[3];
+    for (int a = 0; a < 3; ++a) {
+        flx[a] = (double*)malloc(sizeof(double) * (size_t)n);
+        if (!flx[a]) {
+            for (int b = 0; b < a; ++b) free(flx[b]);
+            return -1;
+        }
+    }
+
+    /* Fluxes through the three "own" faces (+1/2 side) of every cell. */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    int r[3] = {i, j, k};
+                    r[a] += 1;
+                    double vf = facev(p, vel[a], a, c);
+                    flx[a][lin(p, i, j, k)] = donor(cellv(p, phi, c), cellv(p, phi, r), vf);
+                }
+            }
+
+    /* Flux divergence over the metric volume and the update. */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                double dif[3];
+                for (int a = 0; a < 3; ++a) {
+                    int l[3] = {i, j, k};
+                    l[a] -= 1;
+                    dif[a] = facev(p, flx[a], a, c) - facev(p, flx[a], a, l);
+                }
+                int64_t q = lin(p, i, j, k);
+                double div = ((dif[0] + dif[1]) + dif[2]);
+                out[q] = phi[q] - div / g[q];
+            }
+
+    for (int a = 0; a < 3; ++a) free(flx[a]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* C3: antidiffusive pseudo-velocities                                */
+/* ------------------------------------------------------------------ */
+
+/* Velocity on the face of axis t of the cell x (its +1/2 side). */
+static double vel_face(const ref_problem* p, const double* const vel[3], int t, const int x[3])
+{
+    return facev(p, vel[t], t, x);
+}
+
+int ref_antidiff(const ref_problem* p, const double* phi, const double* u,
+                 const double* v, const double* w, const double* g,
+                 double* ut, double* vt, double* wt)
+{
+    if (!valid(p) || !phi || !u || !v || !w || !g || !ut || !vt || !wt) return -1;
+    const double eps = eps_of(p);
+    const double* vel[3] = {u, v, w};
+    double* outv[3] = {ut, vt, wt};
+
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    int L[3] = {i, j, k};
+                    int64_t q = lin(p, i, j, k);
+                    if (is_wall_face(p, a, L[a])) {
+                        outv[a][q] = 0.0;
+                        continue;
+                    }
+                    int R[3] = {i, j, k};
+                    R[a] += 1;
+                    /* transverse axes in increasing order */
+                    int tr[2], nt = 0;
+                    for (int b = 0; b < 3; ++b)
+                        if (b != a) tr[nt++] = b;
+
+                    double pL = cellv(p, phi, L), pR = cellv(p, phi, R);
+                    double A = (pR - pL) / ((pR + pL) + eps);
+
+                    double B[2], Vbar[2];
+                    for (int s = 0; s < 2; ++s) {
+                        int t = tr[s];
+                        int Lp[3] = {L[0], L[1], L[2]}, Rp[3] = {R[0], R[1], R[2]};
+                        int Lm[3] = {L[0], L[1], L[2]}, Rm[3] = {R[0], R[1], R[2]};
+                        Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
+                        double Sp = cellv(p, phi, Rp) + cellv(p, phi, Lp);
+                        double Sm = cellv(p, phi, Rm) + cellv(p, phi, Lm);
+                        B[s] = 0.5 * ((Sp - Sm) / ((Sp + Sm) + eps));
+                        Vbar[s] = 0.25 * ((vel_face(p, vel, t, L) + vel_face(p, vel, t, R))
+                                          + (vel_face(p, vel, t, Lm) + vel_face(p, vel, t, Rm)));
+                    }
+                    double Gf = 0.5 * (cellv(p, g, L) + cellv(p, g, R));
+                    double U = facev(p, vel[a], a, L);
+                    outv[a][q] = ((fabs(U) - (U * U) / Gf) * A)
+                                 - ((U / Gf) * ((Vbar[0] * B[0]) + (Vbar[1] * B[1])));
+                }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* C4: limiter bounds and coefficients                                */
+/* ------------------------------------------------------------------ */
+
+int ref_bounds(const ref_problem* p, const double* psin, const double* phi,
+               double* mx, double* mn)
+{
+    if (!valid(p) || !psin || !phi || !mx || !mn) return -1;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                double hi = psin[lin(p, i, j, k)], lo = hi;
+                /* the 7-point cross of both fields; order does not change the value */
+                for (int f = 0; f < 2; ++f) {
+                    const double* a = f == 0 ? psin : phi;
+                    double s = cellv(p, a, c);
+                    hi = dmax(hi, s);
+                    lo = dmin(lo, s);
+                    for (int ax = 0; ax < 3; ++ax)
+                        for (int sg = -1; sg <= 1; sg += 2) {
+                            int d[3] = {i, j, k};
+                            d[ax] += sg;
+                            double s2 = cellv(p, a, d);
+                            hi = dmax(hi, s2);
+                            lo = dmin(lo, s2);
+                        }
+                }
+                mx[lin(p, i, j, k)] = hi;
+                mn[lin(p, i, j, k)] = lo;
+            }
+    return 0;
+}
+
+int ref_beta(const ref_problem* p, const double* phi, const double* ut,
+             const double* vt, const double* wt, const double* mx,
+             const double* mn, const double* g, double* bup, double* bdn)
+{
+    if (!valid(p) || !phi || !ut || !vt || !wt || !mx || !mn || !g || !bup || !bdn) return -1;
+    const double eps = eps_of(p);
+    const double* vel[3] = {ut, vt, wt};
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                double fin[3], fout[3];
+                for (int a = 0; a < 3; ++a) {
+                    int l[3] = {i, j, k}, r[3] = {i, j, k};
+                    l[a] -= 1;
+                    r[a] += 1;
+                    double vr = facev(p, vel[a], a, c);  /* face +1/2 */
+                    double vl = facev(p, vel[a], a, l);  /* face -1/2 */
+                    /* fp(face) = [v]+ * phi(left), fm(face) = [v]- * phi(right) */
+                    double fp_l = pos(vl) * cellv(p, phi, l);
+                    double fm_l = neg(vl) * cellv(p, phi, c);
+                    double fp_r = pos(vr) * cellv(p, phi, c);
+                    double fm_r = neg(vr) * cellv(p, phi, r);
+                    fin[a] = fp_l - fm_r;
+                    fout[a] = fp_r - fm_l;
+                }
+                int64_t q = lin(p, i, j, k);
+                double in = ((fin[0] + fin[1]) + fin[2]);
+                double out = ((fout[0] + fout[1]) + fout[2]);
+                bup[q] = ((mx[q] - phi[q]) * g[q]) / (in + eps);
+                bdn[q] = ((phi[q] - mn[q]) * g[q]) / (out + eps);
+            }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* C5: limited velocities                                             */
+/* ------------------------------------------------------------------ */
+
+int ref_limit(const ref_problem* p, const double* ut, const double* vt,
+              const double* wt, const double* bup, const double* bdn,
+              double* ul, double* vl, double* wl)
+{
+    if (!valid(p) || !ut || !vt || !wt || !bup || !bdn || !ul || !vl || !wl) return -1;
+    const double* vin[3] = {ut, vt, wt};
+    double* vout[3] = {ul, vl, wl};
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    int L[3] = {i, j, k}, R[3] = {i, j, k};
+                    R[a] += 1;
+                    int64_t q = lin(p, i, j, k);
+                    if (is_wall_face(p, a, L[a])) {
+                        vout[a][q] = 0.0;
+                        continue;
+                    }
+                    double U = vin[a][q];
+                    double up = dmin(1.0, dmin(cellv(p, bdn, L), cellv(p, bup, R)));
+                    double dn = dmin(1.0, dmin(cellv(p, bup, L), cellv(p, bdn, R)));
+                    vout[a][q] = (pos(U) * up) + (neg(U) * dn);
+                }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* C6: the step                                                       */
+/* ------------------------------------------------------------------ */
+
+int ref_step(const ref_problem* p, const double* psin, double* psout,
+             const double* cx, const double* cy, const double* cz,
+             const double* g)
+{
+    if (!valid(p) || !psin || !psout || !cx || !cy || !g || psin == psout) return -1;
+    int64_t n = ncells(p);
+    size_t bytes = sizeof(double) * (size_t)n;
+    double* zero = NULL;
+    if (!cz) {
+        zero = (double*)calloc((size_t)n, sizeof(double));
+        if (!zero) return -1;
+        cz = zero;
+    }
+    /* phi (current iterate), next iterate, velocities of the previous pass,
+     * antidiffusive velocities, bounds and beta */
+    enum { NBUF = 12 };
+    double* buf[NBUF];
+    for (int b = 0; b < NBUF; ++b) {
+        buf[b] = (double*)malloc(bytes);
+        if (!buf[b]) {
+            for (int c = 0; c < b; ++c) free(buf[c]);
+            free(zero);
+            return -1;
+        }
+    }
+    double *phi = buf[0], *nxt = buf[1];
+    double *pu = buf[2], *pv = buf[3], *pw = buf[4];
+    double *au = buf[5], *av = buf[6], *aw = buf[7];
+    double *mx = buf[8], *mn = buf[9], *bup = buf[10], *bdn = buf[11];
+
+    /* pass 1: donor cell with the advective Courant numbers */
+    ref_donor(p, psin, cx, cy, cz, g, phi);
+    memcpy(pu, cx, bytes);
+    memcpy(pv, cy, bytes);
+    memcpy(pw, cz, bytes);
+
+    for (int m = 2; m <= p->iters; ++m) {
+        /* antidiffusive velocities from the current iterate and the
+         * previous pass's velocities */
+        ref_antidiff(p, phi, pu, pv, pw, g, au, av, aw);
+        if (p->limiter) {
+            /* bounds from psi^n and the current iterate, then beta; the
+             * limited velocities become the next pass's "previous" ones */
+            ref_bounds(p, psin, phi, mx, mn);
+            ref_beta(p, phi, au, av, aw, mx, mn, g, bup, bdn);
+            ref_limit(p, au, av, aw, bup, bdn, pu, pv, pw);
+        } else {
+            memcpy(pu, au, bytes);
+            memcpy(pv, av, bytes);
+            memcpy(pw, aw, bytes);
+        }
+        /* the corrective donor pass on phi with the (limited) velocities */
+        ref_donor(p, phi, pu, pv, pw, g, nxt);
+        double* t = phi;
+        phi = nxt;
+        nxt = t;
+    }
+    memcpy(psout, phi, bytes);
+    for (int b = 0; b < NBUF; ++b) free(buf[b]);
+    free(zero);
+    return 0;
+}
+
+int ref_run(const ref_problem* p, int32_t nsteps, double* psi,
+            const double* cx, const double* cy, const double* cz,
+            const double* g)
+{
+    if (!valid(p) || nsteps < 0 || !psi) return -1;
+    if (nsteps == 0) return 0;
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)ncells(p));
+    if (!tmp) return -1;
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = ref_step(p, psi, tmp, cx, cy, cz, g);
+        if (rc) {
+            free(tmp);
+            return rc;
+        }
+        memcpy(psi, tmp, sizeof(double) * (size_t)ncells(p));
+    }
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* C7: mass                                                           */
+/* ------------------------------------------------------------------ */
+
+int ref_mass(const ref_problem* p, const double* psi, const double* g, double* out)
+{
+    if (!valid(p) || !psi || !g || !out) return -1;
+    /* Neumaier: running sum s and compensation c, serial in index order */
+    double s = 0.0, c = 0.0;
+    int64_t n = ncells(p);
+    for (int64_t q = 0; q < n; ++q) {
+        double x = g[q] * psi[q];
+        double t = s + x;
+        if (fabs(s) >= fabs(x))
+            c += (s - t) + x;
+        else
+            c += (x - t) + s;
+        s = t;
+    }
+    *out = s + c;
+    return 0;
+}
+
+int ref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
