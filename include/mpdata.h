@@ -1,0 +1,106 @@
+/*
+ * mpdata.h -- C ABI of libmpdata.so: the MPDATA advection step on a 3-D
+ * structured grid, as hand-written HIP kernels for MI355X (gfx950).
+ *
+ * The operation (paper: ESCAPE D2.5, Section 5, the MPDATA dwarf):
+ *   one time step of  d(G psi)/dt + div(V psi) = 0  made of
+ *   - a donor-cell (upwind) pass: the upwind face flux of Listings 4-5, its
+ *     vertical counterpart of Listings 6-7 (a closed axis is the boundary
+ *     factor 0 there), the flux divergence over the cell's metric volume and
+ *     the solution update of Listing 8;
+ *   - (iters - 1) antidiffusive corrective passes (the MPDATA iterations the
+ *     paper refers to its companion deliverable), each optionally limited by
+ *     the non-oscillatory (flux-corrected transport) limiter.
+ *
+ * Arrays.  psi, g, cx, cy, cz are dense C-order [nz][ny][nx] arrays (i
+ * fastest) of the problem's dtype, in DEVICE memory, contiguous and naturally
+ * aligned.  Staggered face arrays share the cell index space (the C-grid
+ * convention of Section 3.1.4.1): cx[k][j][i] is the Courant number on face
+ * (i+1/2, j, k), cy on (i, j+1/2, k), cz on (i, j, k+1/2).  On a periodic axis
+ * the last slot is the wrap face n-1/2 == -1/2.  On a closed axis the faces
+ * -1/2 and n-1/2 carry no flux and the slot n-1 is never read.  g is the
+ * metric (cell volume factor, the paper's dual volume times density) and must
+ * be > 0.  psi must be >= 0 (the sign-preserving form of the scheme); this is
+ * a precondition and is not checked.
+ *
+ * Ownership.  The caller owns every buffer, including the workspace, whose
+ * size mpdata_workspace_bytes() returns.  These calls never allocate device
+ * memory.  psi_in must not alias psi_out.
+ *
+ * Errors.  Every call validates its arguments synchronously, before anything
+ * is enqueued, and returns MPDATA_OK or a negative code; the reason is then
+ * in mpdata_last_error() (thread-local, valid until the next call on the same
+ * thread).  A failed launch returns MPDATA_EDEVICE.  Faults inside a kernel
+ * surface at the caller's next synchronisation.
+ *
+ * Asynchrony.  Work is enqueued on `stream` (a hipStream_t; NULL = the null
+ * stream) and the calls return after enqueueing, except mpdata_mass, which
+ * synchronises the stream.  Forward calls are bitwise reproducible (no
+ * atomics).
+ */
+#ifndef MPDATA_H
+#define MPDATA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MPDATA_OK = 0,
+    MPDATA_EINVAL = -1,       /* invalid argument, see mpdata_last_error()   */
+    MPDATA_ENOMEM = -2,       /* workspace too small                          */
+    MPDATA_EDEVICE = -3,      /* HIP launch or runtime error                  */
+    MPDATA_EUNSUPPORTED = -4  /* valid but not implemented combination        */
+};
+
+enum { MPDATA_F64 = 0, MPDATA_F32 = 1 };
+enum { MPDATA_PERIODIC = 0, MPDATA_CLOSED = 1 };
+enum { MPDATA_OP_STEP = 0, MPDATA_OP_RUN = 1, MPDATA_OP_ADJOINT = 2, MPDATA_OP_MASS = 3 };
+
+typedef struct {
+    int32_t nx, ny, nz;   /* cells per axis, each >= 1; nz == 1 is a 2-D problem  */
+    int32_t bc[3];        /* per axis x, y, z: MPDATA_PERIODIC or MPDATA_CLOSED    */
+    int32_t iters;        /* passes per step, 1..8: 1 = donor cell only,          */
+                          /* 2 = donor cell + 1 corrective pass, ...              */
+    int32_t limiter;      /* 0 = off, 1 = non-oscillatory limiter on              */
+    int32_t dtype;        /* MPDATA_F64 or MPDATA_F32 (storage and arithmetic)    */
+    int32_t reserved;     /* must be 0                                            */
+    double eps;           /* denominator guard of the antidiffusive and limiter   */
+                          /* ratios; 0 selects 1e-15                              */
+} mpdata_problem;
+
+/* Workspace bytes for `op` (MPDATA_OP_*).  nsteps and checkpoint_every matter
+ * for MPDATA_OP_ADJOINT only.  Returns 0 and sets the error text if p is
+ * invalid. */
+size_t mpdata_workspace_bytes(const mpdata_problem* p, int32_t op, int32_t nsteps,
+                              int32_t checkpoint_every);
+
+/* One step: psi_out = step(psi_in).  cz may be NULL (all vertical Courant
+ * numbers 0).  ws: device workspace of ws_bytes >= the MPDATA_OP_STEP size. */
+int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out,
+                const void* cx, const void* cy, const void* cz, const void* g,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps >= 0 steps in place: psi holds psi^0 on entry and psi^nsteps on
+ * return (after the stream has run).  Winds and metric are the same for all
+ * steps.  ws: at least the MPDATA_OP_RUN size. */
+int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
+               const void* cx, const void* cy, const void* cz, const void* g,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Mass sum(G * psi) accumulated in FP64 (compensated) for either dtype,
+ * written to *host_out.  Synchronises `stream`.  ws: at least the
+ * MPDATA_OP_MASS size. */
+int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g,
+                double* host_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Text of the last error on this thread ("" if none). */
+const char* mpdata_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

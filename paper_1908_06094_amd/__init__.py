@@ -1,0 +1,30 @@
+"""MPDATA advection step on MI355X: Python binding of libmpdata.so.
+
+Argument marshalling only: every stage of the scheme runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  The
+binding fails loudly if the built library is missing; there is no fallback.
+
+Fields are contiguous torch tensors of shape (nz, ny, nx), dtype float64 or
+float32, on a ROCm device.  Boundary conditions are per axis (x, y, z):
+"periodic" or "closed".
+"""
+from __future__ import annotations
+
+from ._lib import (  # noqa: F401
+    MPDATA_CLOSED,
+    MPDATA_F32,
+    MPDATA_F64,
+    MPDATA_OP_MASS,
+    MPDATA_OP_RUN,
+    MPDATA_OP_STEP,
+    MPDATA_PERIODIC,
+    MpdataError,
+    Problem,
+    lib,
+    lib_path,
+    mass,
+    problem_for,
+    run,
+    step,
+    workspace_bytes,
+)

@@ -1,0 +1,164 @@
+"""ctypes binding of the C ABI declared in include/mpdata.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libmpdata.so")
+
+MPDATA_OK, MPDATA_EINVAL, MPDATA_ENOMEM, MPDATA_EDEVICE, MPDATA_EUNSUPPORTED = 0, -1, -2, -3, -4
+MPDATA_F64, MPDATA_F32 = 0, 1
+MPDATA_PERIODIC, MPDATA_CLOSED = 0, 1
+MPDATA_OP_STEP, MPDATA_OP_RUN, MPDATA_OP_ADJOINT, MPDATA_OP_MASS = 0, 1, 2, 3
+
+_BC = {"periodic": MPDATA_PERIODIC, "closed": MPDATA_CLOSED,
+       MPDATA_PERIODIC: MPDATA_PERIODIC, MPDATA_CLOSED: MPDATA_CLOSED}
+
+
+class MpdataError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mpdata error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3), ("iters", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_pp = ctypes.POINTER(Problem)
+
+_SIGNATURES = {
+    "mpdata_workspace_bytes": ([_pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
+    "mpdata_step": ([_pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "mpdata_run": ([_pp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "mpdata_mass": ([_pp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "mpdata_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libmpdata.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_1908_06094_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        handle = ctypes.CDLL(_LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(handle, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = handle
+    return _lib
+
+
+def _check(rc):
+    if rc != MPDATA_OK:
+        msg = lib().mpdata_last_error()
+        raise MpdataError(rc, msg.decode() if msg else "")
+
+
+def problem_for(shape, bc=("periodic", "closed", "closed"), iters=2, limiter=True, dtype="f64", eps=0.0):
+    nz, ny, nx = shape
+    p = Problem()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    for a in range(3):
+        p.bc[a] = _BC[bc[a]]
+    p.iters = int(iters)
+    p.limiter = 1 if limiter else 0
+    p.dtype = {"f64": MPDATA_F64, "f32": MPDATA_F32}[dtype]
+    p.reserved = 0
+    p.eps = float(eps)
+    return p
+
+
+def workspace_bytes(p: Problem, op: int, nsteps: int = 0, checkpoint_every: int = 0) -> int:
+    n = lib().mpdata_workspace_bytes(ctypes.byref(p), op, nsteps, checkpoint_every)
+    if n == 0:
+        _check(MPDATA_EINVAL)
+    return int(n)
+
+
+def _dtype_code(t):
+    import torch
+
+    if t.dtype == torch.float64:
+        return "f64"
+    if t.dtype == torch.float32:
+        return "f32"
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _fields(psi, others):
+    import torch
+
+    if not psi.is_cuda:
+        raise ValueError("fields must be device tensors")
+    for t in (psi, *[o for o in others if o is not None]):
+        if t.shape != psi.shape or t.dtype != psi.dtype or t.device != psi.device:
+            raise ValueError("all fields must share shape, dtype and device")
+        if not t.is_contiguous():
+            raise ValueError("fields must be contiguous")
+    if psi.dim() != 3:
+        raise ValueError("fields must have shape (nz, ny, nx)")
+    return torch.cuda.current_stream(psi.device).cuda_stream
+
+
+def _workspace(nbytes, device):
+    import torch
+
+    # 256-byte aligned by the caching allocator
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def step(psi, cx, cy, cz, g, *, iters=2, limiter=True, bc=("periodic", "closed", "closed"), eps=0.0,
+         out=None, workspace=None):
+    """One MPDATA step on the current stream; returns psi^{n+1} (a new tensor
+    unless `out` is given)."""
+    import torch
+
+    stream = _fields(psi, (cx, cy, cz, g, out))
+    p = problem_for(tuple(psi.shape), bc, iters, limiter, _dtype_code(psi), eps)
+    if out is None:
+        out = torch.empty_like(psi)
+    nb = workspace_bytes(p, MPDATA_OP_STEP)
+    ws = workspace if workspace is not None else _workspace(nb, psi.device)
+    _check(lib().mpdata_step(ctypes.byref(p), _ptr(psi), _ptr(out), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
+                             _ptr(ws), ws.numel(), ctypes.c_void_p(stream)))
+    return out
+
+
+def run(psi, cx, cy, cz, g, nsteps, *, iters=2, limiter=True, bc=("periodic", "closed", "closed"), eps=0.0,
+        workspace=None):
+    """nsteps MPDATA steps in place on psi (enqueued on the current stream)."""
+    stream = _fields(psi, (cx, cy, cz, g))
+    p = problem_for(tuple(psi.shape), bc, iters, limiter, _dtype_code(psi), eps)
+    nb = workspace_bytes(p, MPDATA_OP_RUN)
+    ws = workspace if workspace is not None else _workspace(nb, psi.device)
+    _check(lib().mpdata_run(ctypes.byref(p), int(nsteps), _ptr(psi), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
+                            _ptr(ws), ws.numel(), ctypes.c_void_p(stream)))
+    return psi
+
+
+def mass(psi, g, *, bc=("periodic", "closed", "closed")) -> float:
+    """sum(G psi) accumulated in FP64 on the device (synchronises the stream)."""
+    stream = _fields(psi, (g,))
+    p = problem_for(tuple(psi.shape), bc, 1, False, _dtype_code(psi))
+    ws = _workspace(workspace_bytes(p, MPDATA_OP_MASS), psi.device)
+    out = ctypes.c_double(0.0)
+    _check(lib().mpdata_mass(ctypes.byref(p), _ptr(psi), _ptr(g), ctypes.byref(out), _ptr(ws), ws.numel(),
+                             ctypes.c_void_p(stream)))
+    return out.value

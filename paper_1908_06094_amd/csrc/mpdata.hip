@@ -1,0 +1,366 @@
+// mpdata.hip -- the C ABI of libmpdata.so (declared in include/mpdata.h).
+//
+// Argument validation, workspace layout, the per-step pass driver and the
+// FP64 compensated mass reduction.  Every step of the scheme runs in the HIP
+// kernels of stages.hpp / fused.hpp; the host only validates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "mpdata.h"
+#include "common.hpp"
+#include "stages.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return MPDATA_OK;
+}
+
+constexpr long long kMaxCells = 1LL << 34;   // 17 G cells: far beyond one GPU's HBM in FP32
+constexpr int kMaxIters = 8;
+
+int validate(const mpdata_problem* p)
+{
+    if (!p) return fail(MPDATA_EINVAL, "problem pointer is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(MPDATA_EINVAL, "sizes must be >= 1 (got nx=%d ny=%d nz=%d)", p->nx, p->ny, p->nz);
+    if ((long long)p->nx * p->ny * p->nz > kMaxCells)
+        return fail(MPDATA_EINVAL, "grid of %lld cells exceeds the supported maximum",
+                    (long long)p->nx * p->ny * p->nz);
+    if (p->nz > 65535 || p->ny > 65535 * 4)
+        return fail(MPDATA_EINVAL, "ny=%d / nz=%d exceed the launch grid limits (ny <= 262140, nz <= 65535)",
+                    p->ny, p->nz);
+    for (int a = 0; a < 3; ++a)
+        if (p->bc[a] != MPDATA_PERIODIC && p->bc[a] != MPDATA_CLOSED)
+            return fail(MPDATA_EINVAL, "bc[%d]=%d is neither MPDATA_PERIODIC nor MPDATA_CLOSED", a, p->bc[a]);
+    if (p->iters < 1 || p->iters > kMaxIters)
+        return fail(MPDATA_EINVAL, "iters=%d outside [1, %d]", p->iters, kMaxIters);
+    if (p->limiter != 0 && p->limiter != 1) return fail(MPDATA_EINVAL, "limiter=%d is not 0 or 1", p->limiter);
+    if (p->dtype != MPDATA_F64 && p->dtype != MPDATA_F32)
+        return fail(MPDATA_EINVAL, "dtype=%d is neither MPDATA_F64 nor MPDATA_F32", p->dtype);
+    if (p->reserved != 0) return fail(MPDATA_EINVAL, "reserved field must be 0");
+    if (!(p->eps >= 0.0) || p->eps > 1e-3) return fail(MPDATA_EINVAL, "eps=%g outside [0, 1e-3]", p->eps);
+    return MPDATA_OK;
+}
+
+size_t elem_size(const mpdata_problem* p) { return p->dtype == MPDATA_F64 ? 8 : 4; }
+long long cells(const mpdata_problem* p) { return (long long)p->nx * p->ny * p->nz; }
+
+// Every workspace field starts on a 256-byte boundary.
+size_t field_bytes(const mpdata_problem* p)
+{
+    size_t b = (size_t)cells(p) * elem_size(p);
+    return (b + 255) & ~(size_t)255;
+}
+
+constexpr int kMassBlocks = 1024;
+constexpr int kMassThreads = 256;
+constexpr size_t kMassBytes = (size_t)(kMassBlocks + 1) * 2 * sizeof(double);
+
+// Workspace of one step: two iterates, two velocity triples, two beta fields.
+constexpr int kStepFields = 10;
+
+size_t step_bytes(const mpdata_problem* p) { return kStepFields * field_bytes(p); }
+
+mpdata::Geo geo_of(const mpdata_problem* p)
+{
+    mpdata::Geo g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.closed_x = p->bc[0] == MPDATA_CLOSED;
+    g.closed_y = p->bc[1] == MPDATA_CLOSED;
+    g.closed_z = p->bc[2] == MPDATA_CLOSED;
+    g.sy = p->nx;
+    g.sz = (long long)p->nx * p->ny;
+    return g;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+int check_ptr(const void* ptr, const char* name, const mpdata_problem* p)
+{
+    if (!ptr) return fail(MPDATA_EINVAL, "%s is NULL", name);
+    if (!aligned(ptr, elem_size(p))) return fail(MPDATA_EINVAL, "%s is not aligned to its element size", name);
+    return MPDATA_OK;
+}
+
+int launch_status(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MPDATA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return MPDATA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The pass driver (stage kernels)
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct StepBufs {
+    T* phi[2];
+    T* vel[2][3];
+    T* bup;
+    T* bdn;
+};
+
+template <class T>
+StepBufs<T> carve(const mpdata_problem* p, void* ws)
+{
+    StepBufs<T> b;
+    char* base = (char*)ws;
+    size_t f = field_bytes(p);
+    int n = 0;
+    b.phi[0] = (T*)(base + f * n++);
+    b.phi[1] = (T*)(base + f * n++);
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 3; ++a) b.vel[s][a] = (T*)(base + f * n++);
+    b.bup = (T*)(base + f * n++);
+    b.bdn = (T*)(base + f * n++);
+    return b;
+}
+
+template <class T>
+int step_stages(const mpdata_problem* p, const T* psin, T* psout, const T* cx, const T* cy, const T* cz,
+                const T* gm, void* ws, hipStream_t st)
+{
+    mpdata::Geo g = geo_of(p);
+    StepBufs<T> b = carve<T>(p, ws);
+    const T eps = (T)(p->eps > 0.0 ? p->eps : 1e-15);
+    const double eps_d = p->eps > 0.0 ? p->eps : 1e-15;
+    if (!cz) {
+        // the second velocity triple's w slot is free in pass 1: zero it
+        // (a fill kernel, not a memset node, so the step can be graph-captured)
+        mpdata::k_fill<T><<<1024, 256, 0, st>>>(b.vel[1][2], cells(p), T(0));
+        if (int rc = launch_status("zero vertical velocity")) return rc;
+        cz = b.vel[1][2];
+    }
+    dim3 blk(64, 4, 1);
+    dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
+
+    T* first_out = p->iters == 1 ? psout : b.phi[0];
+    mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    if (int rc = launch_status("donor-cell pass")) return rc;
+    if (p->iters == 1) return ok();
+
+    const T* prev[3] = {cx, cy, cz};
+    const T* phi = b.phi[0];
+    int vsel = 0;
+    for (int m = 2; m <= p->iters; ++m) {
+        T* nxt = (m == p->iters) ? psout : (phi == b.phi[0] ? b.phi[1] : b.phi[0]);
+        T** vq = b.vel[vsel];   // pass 2 writes triple 0, so a zeroed cz in triple 1 survives it
+        mpdata::stages::k_antidiff<T><<<grd, blk, 0, st>>>(g, eps, phi, prev[0], prev[1], prev[2], gm,
+                                                          vq[0], vq[1], vq[2]);
+        if (int rc = launch_status("antidiffusive velocities")) return rc;
+        if (p->limiter) {
+            mpdata::stages::k_beta<T><<<grd, blk, 0, st>>>(g, eps_d, psin, phi, vq[0], vq[1], vq[2], gm,
+                                                          b.bup, b.bdn);
+            if (int rc = launch_status("limiter coefficients")) return rc;
+            mpdata::stages::k_limit<T><<<grd, blk, 0, st>>>(g, vq[0], vq[1], vq[2], b.bup, b.bdn);
+            if (int rc = launch_status("limited velocities")) return rc;
+        }
+        mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, phi, vq[0], vq[1], vq[2], gm, nxt);
+        if (int rc = launch_status("corrective pass")) return rc;
+        prev[0] = vq[0];
+        prev[1] = vq[1];
+        prev[2] = vq[2];
+        phi = nxt;
+        vsel ^= 1;
+    }
+    return ok();
+}
+
+int dispatch_step(const mpdata_problem* p, const void* psin, void* psout, const void* cx, const void* cy,
+                  const void* cz, const void* gm, void* ws, hipStream_t st)
+{
+    if (p->dtype == MPDATA_F64)
+        return step_stages<double>(p, (const double*)psin, (double*)psout, (const double*)cx, (const double*)cy,
+                                   (const double*)cz, (const double*)gm, ws, st);
+    return step_stages<float>(p, (const float*)psin, (float*)psout, (const float*)cx, (const float*)cy,
+                              (const float*)cz, (const float*)gm, ws, st);
+}
+
+// ---------------------------------------------------------------------------
+// Mass: per-thread Neumaier sums in FP64, combined pairwise with an exact
+// two-sum, in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double x)
+{
+    double t = s + x;
+    double bp = t - s;
+    double e = (s - (t - bp)) + (x - bp);
+    s = t;
+    c += e;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kMassThreads) k_mass_partial(long long n, const T* __restrict__ psi,
+                                                               const T* __restrict__ gm, double* __restrict__ part)
+{
+    __shared__ double ss[kMassThreads], sc[kMassThreads];
+    double s = 0.0, c = 0.0;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        two_sum_acc(s, c, (double)gm[q] * (double)psi[q]);
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = kMassThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            double s2 = ss[threadIdx.x], c2 = sc[threadIdx.x] + sc[threadIdx.x + h];
+            two_sum_acc(s2, c2, ss[threadIdx.x + h]);
+            ss[threadIdx.x] = s2;
+            sc[threadIdx.x] = c2;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss[0];
+        part[2 * blockIdx.x + 1] = sc[0];
+    }
+}
+
+__global__ void __launch_bounds__(kMassThreads) k_mass_final(int nparts, double* __restrict__ part)
+{
+    __shared__ double ss[kMassThreads], sc[kMassThreads];
+    double s = 0.0, c = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+        two_sum_acc(s, c, part[2 * b]);
+        c += part[2 * b + 1];
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = kMassThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            double s2 = ss[threadIdx.x], c2 = sc[threadIdx.x] + sc[threadIdx.x + h];
+            two_sum_acc(s2, c2, ss[threadIdx.x + h]);
+            ss[threadIdx.x] = s2;
+            sc[threadIdx.x] = c2;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[2 * nparts] = ss[0] + sc[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exported entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* mpdata_last_error(void) { return g_err.c_str(); }
+
+size_t mpdata_workspace_bytes(const mpdata_problem* p, int32_t op, int32_t nsteps, int32_t checkpoint_every)
+{
+    (void)nsteps;
+    (void)checkpoint_every;
+    if (validate(p) != MPDATA_OK) return 0;
+    switch (op) {
+    case MPDATA_OP_STEP: return step_bytes(p);
+    case MPDATA_OP_RUN: return step_bytes(p) + field_bytes(p);
+    case MPDATA_OP_MASS: return kMassBytes;
+    default: fail(MPDATA_EUNSUPPORTED, "workspace query for op=%d is not supported", op); return 0;
+    }
+}
+
+int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out, const void* cx, const void* cy,
+                const void* cz, const void* g, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (int rc = check_ptr(psi_in, "psi_in", p)) return rc;
+    if (int rc = check_ptr(psi_out, "psi_out", p)) return rc;
+    if (int rc = check_ptr(cx, "cx", p)) return rc;
+    if (int rc = check_ptr(cy, "cy", p)) return rc;
+    if (cz && !aligned(cz, elem_size(p))) return fail(MPDATA_EINVAL, "cz is not aligned to its element size");
+    if (int rc = check_ptr(g, "g", p)) return rc;
+    if (psi_in == psi_out) return fail(MPDATA_EINVAL, "psi_in must not alias psi_out");
+    if (!ws) return fail(MPDATA_EINVAL, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < step_bytes(p))
+        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the step needs", ws_bytes, step_bytes(p));
+    return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, (hipStream_t)stream);
+}
+
+int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* cx, const void* cy, const void* cz,
+               const void* g, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (nsteps < 0) return fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps);
+    if (int rc = check_ptr(psi, "psi", p)) return rc;
+    if (int rc = check_ptr(cx, "cx", p)) return rc;
+    if (int rc = check_ptr(cy, "cy", p)) return rc;
+    if (cz && !aligned(cz, elem_size(p))) return fail(MPDATA_EINVAL, "cz is not aligned to its element size");
+    if (int rc = check_ptr(g, "g", p)) return rc;
+    if (!ws) return fail(MPDATA_EINVAL, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = step_bytes(p) + field_bytes(p);
+    if (ws_bytes < need)
+        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
+    if (nsteps == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    void* alt = (char*)ws + step_bytes(p);
+    void* cur = psi;
+    for (int s = 0; s < nsteps; ++s) {
+        void* nxt = (cur == psi) ? alt : psi;
+        if (int rc = dispatch_step(p, cur, nxt, cx, cy, cz, g, ws, st)) return rc;
+        cur = nxt;
+    }
+    if (cur != psi) {
+        hipError_t e = hipMemcpyAsync(psi, cur, (size_t)cells(p) * elem_size(p), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail(MPDATA_EDEVICE, "final copy: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
+int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g, double* host_out, void* ws,
+                size_t ws_bytes, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (int rc = check_ptr(psi, "psi", p)) return rc;
+    if (int rc = check_ptr(g, "g", p)) return rc;
+    if (!host_out) return fail(MPDATA_EINVAL, "host_out is NULL");
+    if (!ws || !aligned(ws, 8)) return fail(MPDATA_EINVAL, "workspace is NULL or misaligned");
+    if (ws_bytes < kMassBytes)
+        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the mass needs", ws_bytes, kMassBytes);
+    hipStream_t st = (hipStream_t)stream;
+    double* part = (double*)ws;
+    if (p->dtype == MPDATA_F64)
+        k_mass_partial<double><<<kMassBlocks, kMassThreads, 0, st>>>(cells(p), (const double*)psi,
+                                                                      (const double*)g, part);
+    else
+        k_mass_partial<float><<<kMassBlocks, kMassThreads, 0, st>>>(cells(p), (const float*)psi,
+                                                                     (const float*)g, part);
+    if (int rc = launch_status("mass partial sums")) return rc;
+    k_mass_final<<<1, kMassThreads, 0, st>>>(kMassBlocks, part);
+    if (int rc = launch_status("mass final sum")) return rc;
+    hipError_t e = hipMemcpyAsync(host_out, part + 2 * kMassBlocks, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MPDATA_EDEVICE, "mass read-back: %s", hipGetErrorString(e));
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/mpdata.h declares, and rejects invalid arguments
+synchronously with the documented codes before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _mp():
+    import paper_1908_06094_amd as mp
+
+    if not os.path.exists(mp.lib_path()):
+        from paper_1908_06094_amd import build
+
+        build.build()
+    return mp
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(mpdata_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    mp = _mp()
+    handle = ctypes.CDLL(mp.lib_path())
+    declared = _declared()
+    assert {"mpdata_step", "mpdata_run", "mpdata_mass", "mpdata_workspace_bytes", "mpdata_last_error"} <= declared
+    for name in declared:
+        assert hasattr(handle, name), name
+
+
+def _no_device():
+    """Calls below pass bogus device addresses that validation must reject;
+    they are only made where no GPU could ever be reached."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("host-only argument checks (no device calls with bogus pointers on a GPU box)")
+
+
+def _call_step(mp, p, psi_in=8, psi_out=16, ws_bytes=None, ws=256):
+    _no_device()
+    lib = mp.lib()
+    nb = ws_bytes if ws_bytes is not None else 1 << 40
+    v = lambda x: ctypes.c_void_p(x) if x else None
+    return lib.mpdata_step(ctypes.byref(p), v(psi_in), v(psi_out), v(24), v(32), None, v(40), v(ws), nb, None)
+
+
+def test_invalid_problems_rejected():
+    mp = _mp()
+    bad = []
+    p = mp.problem_for((4, 5, 6)); p.nx = 0; bad.append(p)
+    p = mp.problem_for((4, 5, 6)); p.bc[1] = 7; bad.append(p)
+    p = mp.problem_for((4, 5, 6), iters=0); bad.append(p)
+    p = mp.problem_for((4, 5, 6), iters=9); bad.append(p)
+    p = mp.problem_for((4, 5, 6)); p.limiter = 2; bad.append(p)
+    p = mp.problem_for((4, 5, 6)); p.dtype = 5; bad.append(p)
+    p = mp.problem_for((4, 5, 6)); p.reserved = 1; bad.append(p)
+    p = mp.problem_for((4, 5, 6), eps=-1.0); bad.append(p)
+    for p in bad:
+        assert _call_step(mp, p) == mp._lib.MPDATA_EINVAL
+        assert mp.lib().mpdata_last_error()
+        assert mp.lib().mpdata_workspace_bytes(ctypes.byref(p), 0, 0, 0) == 0
+
+
+def test_pointer_and_workspace_checks():
+    mp = _mp()
+    p = mp.problem_for((4, 5, 6))
+    assert _call_step(mp, p, psi_in=None) == mp._lib.MPDATA_EINVAL
+    assert _call_step(mp, p, psi_in=64, psi_out=64) == mp._lib.MPDATA_EINVAL        # aliasing
+    assert b"alias" in mp.lib().mpdata_last_error()
+    assert _call_step(mp, p, psi_in=12) == mp._lib.MPDATA_EINVAL                    # misaligned
+    assert _call_step(mp, p, ws=None) == mp._lib.MPDATA_EINVAL
+    assert _call_step(mp, p, ws=128) == mp._lib.MPDATA_EINVAL                       # ws alignment
+    need = mp.workspace_bytes(p, mp.MPDATA_OP_STEP)
+    assert need > 0
+    assert _call_step(mp, p, ws_bytes=need - 1) == mp._lib.MPDATA_ENOMEM
+    lib = mp.lib()
+    _no_device()
+    assert lib.mpdata_run(ctypes.byref(p), -1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          None, ctypes.c_void_p(8), ctypes.c_void_p(256), 1 << 40, None) == mp._lib.MPDATA_EINVAL
+
+
+def test_workspace_sizes_scale_with_dtype():
+    mp = _mp()
+    p64 = mp.problem_for((10, 20, 30), dtype="f64")
+    p32 = mp.problem_for((10, 20, 30), dtype="f32")
+    a = mp.workspace_bytes(p64, mp.MPDATA_OP_STEP)
+    b = mp.workspace_bytes(p32, mp.MPDATA_OP_STEP)
+    assert a > b > 0
+    assert mp.workspace_bytes(p64, mp.MPDATA_OP_RUN) > a
+
+
+def test_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    mp = _mp()
+    x = torch.ones(2, 3, 4, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        mp.step(x, x, x, x, x)

@@ -1,0 +1,182 @@
+"""GPU vs oracle parity of the MPDATA step, through the C ABI (needs a GPU).
+
+The bar: FP64 results match the CPU FP64 oracle to 1e-12 in the global
+relative max norm ||psi_gpu - psi_ref||_inf / ||psi_ref||_inf, the tolerance
+the scheme's FP64 target states.  Sizes span several kernel tiles and ragged
+tails; the full workload sizes are checked on the exact launch configuration
+the benchmark times.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+P, C = "periodic", "closed"
+TOL64 = 1e-12
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _mp():
+    import paper_1908_06094_amd as mp
+
+    return mp
+
+
+def _dev(a, dtype=None):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    # shape (nz, ny, nx), bc, iters, limiter
+    ((7, 37, 100), (P, C, C), 2, True),
+    ((7, 37, 100), (P, C, C), 3, True),
+    ((5, 19, 131), (C, C, C), 3, True),
+    ((6, 21, 70), (P, P, P), 2, False),
+    ((6, 21, 70), (P, P, P), 4, True),
+    ((9, 13, 65), (C, P, C), 1, False),
+    ((3, 40, 129), (P, C, C), 2, False),
+    ((1, 64, 64), (P, P, P), 2, False),
+    ((12, 5, 3), (P, C, P), 3, True),
+    ((1, 1, 1), (P, P, P), 2, True),
+    ((4, 1, 200), (P, C, C), 3, True),
+]
+
+
+@pytest.mark.parametrize("shape,bc,iters,lim", CASES)
+def test_step_matches_oracle(shape, bc, iters, lim):
+    torch = _torch()
+    mp = _mp()
+    _say(f"[parity] step shape={shape} bc={bc} iters={iters} limiter={lim}")
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=hash((shape, iters)) % 1000, courant=0.8)
+    p = oracle.RefProblem(shape[2], shape[1], shape[0], bc=bc, iters=iters, limiter=lim)
+    want = oracle.step(p, psi, cx, cy, cz, g)
+    got = mp.step(_dev(psi), _dev(cx), _dev(cy), _dev(cz), _dev(g), iters=iters, limiter=lim, bc=bc)
+    torch.cuda.synchronize()
+    assert _rel(got.cpu().numpy(), want) <= TOL64
+
+
+@pytest.mark.parametrize("shape,bc,iters,lim", CASES[:4])
+def test_run_matches_oracle(shape, bc, iters, lim):
+    torch = _torch()
+    mp = _mp()
+    _say(f"[parity] run shape={shape} bc={bc} iters={iters} limiter={lim}")
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=7, courant=0.8)
+    p = oracle.RefProblem(shape[2], shape[1], shape[0], bc=bc, iters=iters, limiter=lim)
+    want = oracle.run(p, 9, psi, cx, cy, cz, g)
+    t = _dev(psi)
+    mp.run(t, _dev(cx), _dev(cy), _dev(cz), _dev(g), 9, iters=iters, limiter=lim, bc=bc)
+    torch.cuda.synchronize()
+    assert _rel(t.cpu().numpy(), want) <= TOL64
+
+
+def test_cz_none_equals_zero_field():
+    torch = _torch()
+    mp = _mp()
+    shape = (5, 17, 90)
+    psi, cx, cy, _, g = workloads.random_problem(shape, (P, C, C), seed=3)
+    z = np.zeros(shape)
+    a = mp.step(_dev(psi), _dev(cx), _dev(cy), None, _dev(g), iters=3)
+    b = mp.step(_dev(psi), _dev(cx), _dev(cy), _dev(z), _dev(g), iters=3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_deterministic_and_resumable():
+    torch = _torch()
+    mp = _mp()
+    shape = (6, 30, 77)
+    psi, cx, cy, cz, g = workloads.random_problem(shape, (P, C, C), seed=4)
+    args = [_dev(x) for x in (cx, cy, cz, g)]
+    a = _dev(psi)
+    mp.run(a, *args, 10, iters=3)
+    b = _dev(psi)
+    mp.run(b, *args, 10, iters=3)
+    c = _dev(psi)
+    mp.run(c, *args, 5, iters=3)
+    mp.run(c, *args, 5, iters=3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_mass_matches_exact_sum():
+    _torch()
+    mp = _mp()
+    shape = (7, 45, 123)
+    psi, _, _, _, g = workloads.random_problem(shape, (P, C, C), seed=6)
+    got = mp.mass(_dev(psi), _dev(g))
+    want = math.fsum((g * psi).ravel().tolist())
+    assert abs(got - want) <= 1e-15 * abs(want)
+
+
+def test_config1_full_run():
+    torch = _torch()
+    mp = _mp()
+    w = workloads.config1()
+    _say(f"[parity] {w.name} {w.steps} steps")
+    p = oracle.RefProblem(64, 64, 1, bc=w.bc, iters=w.iters, limiter=w.limiter)
+    want = oracle.run(p, w.steps, w.psi, w.cx, w.cy, w.cz, w.g)
+    t = _dev(w.psi)
+    mp.run(t, _dev(w.cx), _dev(w.cy), _dev(w.cz), _dev(w.g), w.steps, iters=w.iters, limiter=w.limiter, bc=w.bc)
+    torch.cuda.synchronize()
+    assert _rel(t.cpu().numpy(), want) <= TOL64
+
+
+def test_config2_full_run():
+    torch = _torch()
+    mp = _mp()
+    w = workloads.config2()
+    _say(f"[parity] {w.name} {w.steps} steps, oracle threads={oracle.num_threads()}")
+    p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
+    want = oracle.run(p, w.steps, w.psi, w.cx, w.cy, w.cz, w.g)
+    t = _dev(w.psi)
+    args = [_dev(x) for x in (w.cx, w.cy, w.cz, w.g)]
+    m0 = mp.mass(t, args[3])
+    mp.run(t, *args, w.steps, iters=w.iters, limiter=w.limiter, bc=w.bc)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    assert _rel(got, want) <= TOL64
+    assert got.min() >= 0.0
+    assert abs(mp.mass(t, args[3]) - m0) <= 1e-13 * m0
+
+
+def test_config3_full_size_one_step():
+    """The benchmark's workload (1024x512x80, 3 passes, limiter) at full size:
+    two steps against the oracle, every cell compared."""
+    torch = _torch()
+    mp = _mp()
+    w = workloads.config3()
+    _say(f"[parity] {w.name} 2 steps at full size")
+    p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
+    want = oracle.run(p, 2, w.psi, w.cx, w.cy, w.cz, w.g)
+    t = _dev(w.psi)
+    mp.run(t, *[_dev(x) for x in (w.cx, w.cy, w.cz, w.g)], 2, iters=w.iters, limiter=w.limiter, bc=w.bc)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    assert _rel(got, want) <= TOL64
+    assert got.min() >= 0.0
