@@ -13,6 +13,7 @@
 #include "mpdata.h"
 #include "common.hpp"
 #include "stages.hpp"
+#include "fused.hpp"
 
 namespace {
 
