@@ -10,10 +10,14 @@
 // applies to the upwind stages (Section 6.1, Table 2, Listing 9).
 //
 // Mapping onto gfx950:
-//   * a workgroup is 16 waves of 64 lanes; lane = x, wave = y.  It owns a
-//     60 x 12 interior tile plus a halo of 2 and marches up the k axis, so
+//   * a workgroup is 12 waves of 64 lanes; lane = x, wave = y.  It owns a
+//     60 x 8 interior tile plus a halo of 2 and marches up the k axis, so
 //     each stage is computed once per column and plane (no halo recompute
-//     along k);
+//     along k).  Its LDS (114 KB in FP64) allows one workgroup per CU;
+//     12 waves leave each wave 168 VGPRs, enough to keep a column's plane
+//     history in registers without spilling;
+//   * persistent launch: one workgroup per CU, each marching an equal share
+//     of the (tile, plane) space, ranges grouped by XCD;
 //   * x neighbours come from DPP lane shifts (wave_shl / wave_shr), y
 //     neighbours from one LDS plane slot per exchanged quantity, k neighbours
 //     from the column's own register history;
@@ -34,11 +38,11 @@ namespace mpdata {
 namespace fused {
 
 constexpr int kLanes = 64;               // x extent of a tile, halo included
-constexpr int kRows = 16;                // y extent (waves per workgroup)
+constexpr int kRows = 12;                // y extent (waves per workgroup)
 constexpr int kHalo = 2;
 constexpr int kTileX = kLanes - 2 * kHalo;   // 60 interior columns
-constexpr int kTileY = kRows - 2 * kHalo;    // 12 interior rows
-constexpr int kThreads = kLanes * kRows;     // 1024
+constexpr int kTileY = kRows - 2 * kHalo;    // 8 interior rows
+constexpr int kThreads = kLanes * kRows;     // 768: 3 waves per SIMD, up to 168 VGPRs each
 
 // ---------------------------------------------------------------------------
 // Lane shifts.  next(v): lane l receives lane l+1's value; prev(v): lane l-1's.
@@ -102,7 +106,18 @@ __device__ __forceinline__ void beta_pair(T hi, T lo, T phi, T g, T fin, T fout,
     bdn = (T)(((double)((phi - lo) * g) * a) * r);
 }
 
-template <class T> __device__ __forceinline__ T min3(T a, T b, T c) { return min2(a, min2(b, c)); }
+
+// [c]+ and [c]- as single v_max / v_min instructions (the sign of a zero
+// result may differ from a compare-and-select; no value does)
+__device__ __forceinline__ double pos_f(double c) { return __builtin_fmax(c, 0.0); }
+__device__ __forceinline__ double neg_f(double c) { return __builtin_fmin(c, 0.0); }
+__device__ __forceinline__ float pos_f(float c) { return __builtin_fmaxf(c, 0.0f); }
+__device__ __forceinline__ float neg_f(float c) { return __builtin_fminf(c, 0.0f); }
+__device__ __forceinline__ double fmx(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double fmn(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float fmx(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ float fmn(float a, float b) { return __builtin_fminf(a, b); }
+template <class T> __device__ __forceinline__ T min3(T a, T b, T c) { return fmn(a, fmn(b, c)); }
 
 // Workgroup barrier ordering LDS only: prefetched global loads stay in flight.
 __device__ __forceinline__ void lds_barrier()
@@ -145,12 +160,28 @@ __device__ __forceinline__ bool wall_face(int x, int n, int closed) { return clo
 
 template <class T>
 struct Slots {
-    // y-exchange planes, one value per (row, lane)
-    T phi[kRows][kLanes], u[kRows][kLanes], w[kRows][kLanes], g[kRows][kLanes];
-    T px[kRows][kLanes], vpx[kRows][kLanes], pz[kRows][kLanes], vpz[kRows][kLanes];
+    // y-exchange planes, one value per (row, lane); phi, px and vpx keep the
+    // last two planes (slot = plane parity) so that plane k's neighbours are
+    // read one march step after they were published
+    T phi[2][kRows][kLanes], px[2][kRows][kLanes], vpx[2][kRows][kLanes];
+    T u[kRows][kLanes], w[kRows][kLanes], g[kRows][kLanes];
+    T pz[kRows][kLanes], vpz[kRows][kLanes];
     T mx[kRows][kLanes], mn[kRows][kLanes], fpy[kRows][kLanes], fmy[kRows][kLanes];
     T bup[kRows][kLanes], bdn[kRows][kLanes];
     T fy[2][kRows][kLanes];
+};
+
+// One column's values of one plane: the loaded fields and what is derived
+// from them.  Three banks hold the planes k-1, k and k+1.
+template <class T>
+struct Bank {
+    T phi, u, v, w, g;                     // loaded
+    T px, py, vpx, wpx, wpy, upy, gpy;     // pair sums (see the face formulas)
+    T mx, mn;                              // max / min of psi^n and phi
+};
+template <class T>
+struct Raw {
+    T phi, psin, u, v, w, g;
 };
 
 template <class T, bool LIMIT, bool WRITE_VEL>
@@ -162,204 +193,204 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
     const int row = threadIdx.x >> 6;
     const int up = row < kRows - 1 ? row + 1 : row;     // clamped: the edge rows are halo
     const int dn = row > 0 ? row - 1 : row;
-
-    const int tile = blockIdx.x;
-    const int tx = tile % a.tiles_x;
-    const int ty = tile / a.tiles_x;
-    const int gi = tx * kTileX - kHalo + lane;           // virtual column of this lane
-    const int gj = ty * kTileY - kHalo + row;
-    const int ci = map_index(gi, geo.nx, geo.closed_x);
-    const int cj = map_index(gj, geo.ny, geo.closed_y);
-    const bool xwall = wall_face(gi, geo.nx, geo.closed_x);
-    const bool ywall = wall_face(gj, geo.ny, geo.closed_y);
-    const long long col = (long long)cj * geo.sy + ci;
-    const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
-                        gi < geo.nx && gj < geo.ny;
-
     const T eps = (T)a.eps;
     const T zero = T(0);
 
-    // plane loader: cell quantities through the halo rule, faces masked at walls
-    struct Plane {
-        T phi, psin, u, v, w, g;
-    };
-    auto load = [&](int k) {
-        Plane p;
-        const int ck = map_index(k, geo.nz, geo.closed_z);
-        const long long q = (long long)ck * geo.sz + col;
-        p.phi = a.phi[q];
-        p.psin = LIMIT ? a.psin[q] : zero;
-        p.u = xwall ? zero : a.u[q];
-        p.v = ywall ? zero : a.v[q];
-        p.w = (a.w == nullptr || wall_face(k, geo.nz, geo.closed_z)) ? zero : a.w[q];
-        p.g = a.g[q];
-        return p;
-    };
+    // Work split: the (tile, output plane) pairs in tile-major order are cut
+    // into equal contiguous ranges, one per workgroup, so every workgroup
+    // marches the same number of planes (a range may span a tile boundary).
+    // Workgroups are dispatched round-robin over the 8 XCDs; consecutive
+    // ranges go to one XCD so that neighbouring tiles share its L2.
+    const int nwg = gridDim.x;                         // a multiple of 8
+    const int wg = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+    const long long total = (long long)a.tiles_x * a.tiles_y * geo.nz;
+    const long long span = (total + nwg - 1) / nwg;
+    long long w0 = (long long)wg * span;
+    const long long w1 = w0 + span < total ? w0 + span : total;
 
-    // ---- register history of this column ----
-    // plane k+1 ("n"), k ("c"), k-1 ("p"), where k = t-1 is the plane whose
-    // antidiffusive velocities and beta are formed in march step t
-    T phi_p = 0, phi_c = 0, phi_n = 0, nphi_c = 0, nphi_n = 0;
-    T u_c = 0, u_n = 0, v_c = 0, v_n = 0, w_c = 0, w_n = 0;
-    T g_p = 0, g_c = 0, g_n = 0, gx_c = 0, gx_n = 0;
-    T px_p = 0, px_c = 0, px_n = 0, px_c_up = 0, px_c_dn = 0, px_n_up = 0, px_n_dn = 0;
-    T py_p = 0, py_c = 0, py_n = 0;
-    T phiup_c = 0, phiup_n = 0;
-    T vpx_c = 0, vpx_n = 0, vpxdn_c = 0, vpxdn_n = 0;
-    T wpx_p = 0, wpx_c = 0, wpx_n = 0, wpy_p = 0, wpy_c = 0, wpy_n = 0;
-    T upy_c = 0, upy_n = 0, gpy_c = 0, gpy_n = 0;
-    T mx_p = 0, mx_c = 0, mx_n = 0, mn_p = 0, mn_c = 0, mn_n = 0;
-    T uz_p = 0;                 // antidiffusive velocity at face k-1/2
-    T bup_p = 0, bdn_p = 0;     // beta at plane k-1
-    T ulx_p = 0, uly_p = 0;     // limited x/y velocities at plane k-1
-    T fx_p = 0, fy_p = 0;       // x and y fluxes at plane k-1
-    T fz_pp = 0;                // z flux at face k-3/2
+    while (w0 < w1) {
+        const int tile = (int)(w0 / geo.nz);
+        const int kb = (int)(w0 - (long long)tile * geo.nz);
+        const int ke = (int)((long long)kb + (w1 - w0) < geo.nz ? kb + (w1 - w0) : geo.nz);
+        w0 += ke - kb;
 
-    const int kb = 0, ke = geo.nz;
-    int par = 0;                // parity of the Fy slot written in this step
+        const int tx = tile % a.tiles_x;
+        const int ty = tile / a.tiles_x;
+        const int gi = tx * kTileX - kHalo + lane;       // virtual column of this lane
+        const int gj = ty * kTileY - kHalo + row;
+        const int ci = map_index(gi, geo.nx, geo.closed_x);
+        const int cj = map_index(gj, geo.ny, geo.closed_y);
+        const bool xwall = wall_face(gi, geo.nx, geo.closed_x);
+        const bool ywall = wall_face(gj, geo.ny, geo.closed_y);
+        const long long col = (long long)cj * geo.sy + ci;
+        const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
+                            gi < geo.nx && gj < geo.ny;
 
-    Plane nx_ = load(kb - 3);
-    for (int t = kb - 3; t <= ke + 1; ++t) {
-        // ---------------- phase 0: plane t arrives ----------------
-        const Plane pl = nx_;
-        if (t + 1 <= ke + 1) nx_ = load(t + 1);     // prefetch the next plane
+        // plane loader: cell quantities through the halo rule, faces masked at walls
+        auto load = [&](int k, Raw<T>& B) __attribute__((always_inline)) {
+            const int ck = map_index(k, geo.nz, geo.closed_z);
+            const long long q = (long long)ck * geo.sz + col;
+            B.phi = a.phi[q];
+            B.psin = LIMIT ? a.psin[q] : zero;
+            B.u = xwall ? zero : a.u[q];
+            B.v = ywall ? zero : a.v[q];
+            B.w = (a.w == nullptr || wall_face(k, geo.nz, geo.closed_z)) ? zero : a.w[q];
+            B.g = a.g[q];
+        };
 
-        // rotate: n -> c -> p
-        phi_p = phi_c; phi_c = phi_n; phi_n = pl.phi;
-        nphi_c = nphi_n; nphi_n = lane_next(pl.phi);
-        u_c = u_n; u_n = pl.u;
-        v_c = v_n; v_n = pl.v;
-        w_c = w_n; w_n = pl.w;
-        g_p = g_c; g_c = g_n; g_n = pl.g;
-        gx_c = gx_n; gx_n = pl.g + lane_next(pl.g);
-        px_p = px_c; px_c = px_n; px_n = nphi_n + pl.phi;
-        px_c_up = px_n_up; px_c_dn = px_n_dn;
-        py_p = py_c; py_c = py_n;
-        phiup_c = phiup_n;
-        vpx_c = vpx_n; vpx_n = pl.v + lane_next(pl.v);
-        vpxdn_c = vpxdn_n;
-        wpx_p = wpx_c; wpx_c = wpx_n; wpx_n = pl.w + lane_next(pl.w);
-        wpy_p = wpy_c; wpy_c = wpy_n;
-        upy_c = upy_n;
-        gpy_c = gpy_n;
-        if (LIMIT) {
-            mx_p = mx_c; mx_c = mx_n; mx_n = max2(pl.psin, pl.phi);
-            mn_p = mn_c; mn_c = mn_n; mn_n = min2(pl.psin, pl.phi);
-        }
-        const T pz_c = phi_n + phi_c;      // z face k+1/2: + side (k+1) first
-        const T vpz_c = v_c + v_n;         // lower cell first
-        const T upz_c = u_c + u_n;
+        Bank<T> B0{}, B1{}, B2{};
+        Raw<T> R{};
+        T wsx = 0, wsy = 0;         // wpx and wpy summed over planes k and k-1
+        T uz_p = 0;                 // antidiffusive velocity at face k-1/2
+        T bup_p = 0, bdn_p = 0;     // beta at plane k-1
+        T fx_p = 0, fy_p = 0;       // x and y fluxes at plane k-1
+        T fz_pp = 0;                // z flux at face k-3/2
+        const int t_last = ke + 1;
 
-        S.phi[row][lane] = pl.phi;
-        S.u[row][lane] = pl.u;
-        S.w[row][lane] = pl.w;
-        S.g[row][lane] = pl.g;
-        S.px[row][lane] = px_n;
-        S.vpx[row][lane] = vpx_n;
-        S.pz[row][lane] = pz_c;
-        S.vpz[row][lane] = vpz_c;
-        lds_barrier();
-
-        // ---------------- phase 1: y neighbours of plane t, velocities of plane k ----------------
-        phiup_n = S.phi[up][lane];
-        py_n = phiup_n + pl.phi;
-        upy_n = pl.u + S.u[up][lane];
-        wpy_n = pl.w + S.w[up][lane];
-        gpy_n = pl.g + S.g[up][lane];
-        px_n_up = S.px[up][lane];
-        px_n_dn = S.px[dn][lane];
-        vpxdn_n = S.vpx[dn][lane];
-        const T pz_up = S.pz[up][lane];
-        const T pz_dn = S.pz[dn][lane];
-        const T vpz_dn = S.vpz[dn][lane];
-
-        // x face (i+1/2, j, k): transverse y then z
-        const T ux = antidiff_face(nphi_c - phi_c, px_c + eps,
-                                   px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
-                                   px_n - px_p, (px_n + px_p) + eps,
-                                   vpx_c + vpxdn_c, wpx_c + wpx_p, gx_c, u_c);
-        // y face (i, j+1/2, k): transverse x then z
-        const T py_nx = lane_next(py_c), py_pv = lane_prev(py_c);
-        const T uy = antidiff_face(phiup_c - phi_c, py_c + eps,
-                                   py_nx - py_pv, (py_nx + py_pv) + eps,
-                                   py_n - py_p, (py_n + py_p) + eps,
-                                   upy_c + lane_prev(upy_c), wpy_c + wpy_p, gpy_c, v_c);
-        // z face (i, j, k+1/2): transverse x then y
-        const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
-        const T uz = antidiff_face(phi_n - phi_c, pz_c + eps,
-                                   pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
-                                   pz_up - pz_dn, (pz_up + pz_dn) + eps,
-                                   upz_c + lane_prev(upz_c), vpz_c + vpz_dn, g_c + g_n, w_c);
-
-        T ulx, uly, ulz;       // limited velocities: x, y at plane k; z at face k-1/2
-        if (LIMIT) {
-            const T fpy = pos_part(uy) * phi_c;
-            const T fmy = neg_part(uy) * phiup_c;
-            S.mx[row][lane] = mx_c;
-            S.mn[row][lane] = mn_c;
-            S.fpy[row][lane] = fpy;
-            S.fmy[row][lane] = fmy;
-            lds_barrier();
-
-            // ---------------- phase 2: bounds, in/out, beta at plane k ----------------
-            T hi = max2(max2(mx_c, max2(lane_next(mx_c), lane_prev(mx_c))),
-                        max2(max2(S.mx[up][lane], S.mx[dn][lane]), max2(mx_p, mx_n)));
-            T lo = min2(min2(mn_c, min2(lane_next(mn_c), lane_prev(mn_c))),
-                        min2(min2(S.mn[up][lane], S.mn[dn][lane]), min2(mn_p, mn_n)));
-            const T fpx = pos_part(ux) * phi_c;
-            const T fmx = neg_part(ux) * nphi_c;
-            const T fpz = pos_part(uz) * phi_c;
-            const T fmz = neg_part(uz) * phi_n;
-            const T fpz_l = pos_part(uz_p) * phi_p;
-            const T fmz_l = neg_part(uz_p) * phi_c;
-            const T fin = ((lane_prev(fpx) - fmx) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
-            const T fout = ((fpx - lane_prev(fmx)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
-            T bup, bdn;
-            beta_pair<T>(hi, lo, phi_c, g_c, fin, fout, a.eps, bup, bdn);
-            S.bup[row][lane] = bup;
-            S.bdn[row][lane] = bdn;
-            lds_barrier();
-
-            // ---------------- phase 3a: limited velocities ----------------
-            const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
-            ulx = pos_part(ux) * min3(T(1), bdn, lane_next(bup)) + neg_part(ux) * min3(T(1), bup, lane_next(bdn));
-            uly = pos_part(uy) * min3(T(1), bdn, bup_up) + neg_part(uy) * min3(T(1), bup, bdn_up);
-            ulz = pos_part(uz_p) * min3(T(1), bdn_p, bup) + neg_part(uz_p) * min3(T(1), bup_p, bdn);
-            bup_p = bup;
-            bdn_p = bdn;
-        } else {
-            ulx = ux;
-            uly = uy;
-            ulz = uz_p;
-        }
-
-        // ---------------- phase 3b: donor-cell update of plane k-1 ----------------
-        const T fx_c = pos_part(ulx) * phi_c + neg_part(ulx) * nphi_c;
-        const T fy_c = pos_part(uly) * phi_c + neg_part(uly) * phiup_c;
-        S.fy[par][row][lane] = fy_c;
-        const T fz_h = pos_part(ulz) * phi_p + neg_part(ulz) * phi_c;     // face k-1/2
-        const T fy_p_dn = S.fy[par ^ 1][dn][lane];
-        const T fx_p_l = lane_prev(fx_p);      // all lanes: DPP reads need every source lane active
-        const int ko = t - 2;                  // plane k-1
-        if (writer && ko >= kb && ko < ke) {
-            const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
-            const long long q = (long long)ko * geo.sz + col;
-            a.out[q] = phi_p - div / g_p;
-            if (WRITE_VEL) {
-                a.ul[q] = ulx_p;
-                a.vl[q] = uly_p;
-                a.wl[q] = ulz;                 // face (k-1)+1/2
+        // March step t: plane t (bank N) has arrived; velocities and beta of
+        // plane k = t-1 (bank C) are formed, and plane k-1 (bank P) is updated.
+        auto step = [&](const int t, Bank<T>& P, Bank<T>& C, Bank<T>& N) __attribute__((always_inline)) {
+            // ---------------- phase 0: plane t arrives ----------------
+            N.phi = R.phi;
+            N.u = R.u;
+            N.v = R.v;
+            N.w = R.w;
+            N.g = R.g;
+            const T psin_n = R.psin;
+            if (t + 1 <= t_last) load(t + 1, R);    // prefetch the next plane
+            const int sn = t & 1, sc = sn ^ 1;      // ring slots of planes t (= k+1) and k
+            N.px = lane_next(N.phi) + N.phi;
+            N.vpx = N.v + lane_next(N.v);
+            N.wpx = N.w + lane_next(N.w);
+            if (LIMIT) {
+                N.mx = fmx(psin_n, N.phi);
+                N.mn = fmn(psin_n, N.phi);
             }
+            const T pz_c = N.phi + C.phi;     // z face k+1/2: + side (k+1) first
+            const T vpz_c = C.v + N.v;        // lower cell first
+            const T upz_c = C.u + N.u;
+            S.phi[sn][row][lane] = N.phi;
+            S.u[row][lane] = N.u;
+            S.w[row][lane] = N.w;
+            S.g[row][lane] = N.g;
+            S.px[sn][row][lane] = N.px;
+            S.vpx[sn][row][lane] = N.vpx;
+            S.pz[row][lane] = pz_c;
+            S.vpz[row][lane] = vpz_c;
+            lds_barrier();
+
+            // ---------------- phase 1: y neighbours, antidiffusive velocities of plane k ----------------
+            N.py = S.phi[sn][up][lane] + N.phi;
+            N.upy = N.u + S.u[up][lane];
+            N.wpy = N.w + S.w[up][lane];
+            N.gpy = N.g + S.g[up][lane];
+            const T px_c_up = S.px[sc][up][lane];
+            const T px_c_dn = S.px[sc][dn][lane];
+            const T vpxdn_c = S.vpx[sc][dn][lane];
+            const T phiup_c = S.phi[sc][up][lane];
+            const T pz_up = S.pz[up][lane];
+            const T pz_dn = S.pz[dn][lane];
+            const T vpz_dn = S.vpz[dn][lane];
+            const T nphi_c = lane_next(C.phi);
+            const T gx_c = C.g + lane_next(C.g);
+
+            // x face (i+1/2, j, k): transverse y then z
+            const T ux = antidiff_face(nphi_c - C.phi, C.px + eps,
+                                       px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
+                                       N.px - P.px, (N.px + P.px) + eps,
+                                       C.vpx + vpxdn_c, wsx, gx_c, C.u);
+            // y face (i, j+1/2, k): transverse x then z
+            const T py_nx = lane_next(C.py), py_pv = lane_prev(C.py);
+            const T uy = antidiff_face(phiup_c - C.phi, C.py + eps,
+                                       py_nx - py_pv, (py_nx + py_pv) + eps,
+                                       N.py - P.py, (N.py + P.py) + eps,
+                                       C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
+            // z face (i, j, k+1/2): transverse x then y
+            const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
+            const T uz = antidiff_face(N.phi - C.phi, pz_c + eps,
+                                       pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
+                                       pz_up - pz_dn, (pz_up + pz_dn) + eps,
+                                       upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
+
+            T ulx, uly, ulz;       // limited velocities: x, y at plane k; z at face k-1/2
+            if (LIMIT) {
+                const T fpy = pos_f(uy) * C.phi;
+                const T fmy = neg_f(uy) * phiup_c;
+                S.mx[row][lane] = C.mx;
+                S.mn[row][lane] = C.mn;
+                S.fpy[row][lane] = fpy;
+                S.fmy[row][lane] = fmy;
+                lds_barrier();
+
+                // ---------------- phase 2: bounds, in/out, beta at plane k ----------------
+                const T hi = fmx(fmx(C.mx, fmx(lane_next(C.mx), lane_prev(C.mx))),
+                                 fmx(fmx(S.mx[up][lane], S.mx[dn][lane]), fmx(P.mx, N.mx)));
+                const T lo = fmn(fmn(C.mn, fmn(lane_next(C.mn), lane_prev(C.mn))),
+                                 fmn(fmn(S.mn[up][lane], S.mn[dn][lane]), fmn(P.mn, N.mn)));
+                const T fpx = pos_f(ux) * C.phi;
+                const T fmx_ = neg_f(ux) * nphi_c;
+                const T fpz = pos_f(uz) * C.phi;
+                const T fmz = neg_f(uz) * N.phi;
+                const T fpz_l = pos_f(uz_p) * P.phi;
+                const T fmz_l = neg_f(uz_p) * C.phi;
+                const T fin = ((lane_prev(fpx) - fmx_) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
+                const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
+                T bup, bdn;
+                beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
+                S.bup[row][lane] = bup;
+                S.bdn[row][lane] = bdn;
+                lds_barrier();
+
+                // ---------------- phase 3a: limited velocities ----------------
+                const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
+                ulx = pos_f(ux) * min3(T(1), bdn, lane_next(bup)) + neg_f(ux) * min3(T(1), bup, lane_next(bdn));
+                uly = pos_f(uy) * min3(T(1), bdn, bup_up) + neg_f(uy) * min3(T(1), bup, bdn_up);
+                ulz = pos_f(uz_p) * min3(T(1), bdn_p, bup) + neg_f(uz_p) * min3(T(1), bup_p, bdn);
+                bup_p = bup;
+                bdn_p = bdn;
+            } else {
+                ulx = ux;
+                uly = uy;
+                ulz = uz_p;
+            }
+
+            // ---------------- phase 3b: donor-cell update of plane k-1 ----------------
+            const int par = t & 1;
+            const T fx_c = pos_f(ulx) * C.phi + neg_f(ulx) * nphi_c;
+            const T fy_c = pos_f(uly) * C.phi + neg_f(uly) * phiup_c;
+            S.fy[par][row][lane] = fy_c;
+            const T fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
+            const T fy_p_dn = S.fy[par ^ 1][dn][lane];
+            const T fx_p_l = lane_prev(fx_p);      // every lane: DPP needs its source lanes active
+            const int ko = t - 2;                  // plane k-1
+            if (writer && ko >= kb && ko < ke) {
+                const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
+                const long long q = (long long)ko * geo.sz + col;
+                a.out[q] = P.phi - div / P.g;
+                if (WRITE_VEL) a.wl[q] = ulz;      // face (k-1)+1/2
+            }
+            if (WRITE_VEL && writer && ko + 1 >= kb && ko + 1 < ke) {
+                const long long q = (long long)(ko + 1) * geo.sz + col;   // plane k
+                a.ul[q] = ulx;
+                a.vl[q] = uly;
+            }
+            fz_pp = fz_h;
+            wsx = N.wpx + C.wpx;
+            wsy = N.wpy + C.wpy;
+            fx_p = fx_c;
+            fy_p = fy_c;
+            uz_p = uz;
+            if (!LIMIT) lds_barrier();   // phase-0 slots are rewritten next; with the limiter the
+                                         // phase-2 and phase-3 barriers already separate them
+        };
+
+        load(kb - 3, R);
+        for (int t = kb - 3; t <= t_last; ++t) {
+            step(t, B0, B1, B2);
+            B0 = B1;
+            B1 = B2;
         }
-        fz_pp = fz_h;
-        fx_p = fx_c;
-        fy_p = fy_c;
-        ulx_p = ulx;
-        uly_p = uly;
-        uz_p = uz;
-        par ^= 1;
-        if (!LIMIT) lds_barrier();   // phase-0 slots are rewritten next; with the limiter the
-                                     // phase-2 and phase-3 barriers already separate them
+        lds_barrier();   // the next segment rewrites every slot
     }
 }
 

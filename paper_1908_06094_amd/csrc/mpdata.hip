@@ -7,6 +7,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -191,14 +192,110 @@ int step_stages(const mpdata_problem* p, const T* psin, T* psout, const T* cx, c
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// The fused driver: donor-cell pass, then one k-marching kernel per
+// corrective pass.
+// ---------------------------------------------------------------------------
+
+// Compute units of the current device (cached per device).
+int cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+// Persistent grid of the fused passes: one workgroup per CU (their LDS
+// allows no more), a multiple of 8 (the XCD count the work split groups by),
+// and no more workgroups than leave each at least ~12 output planes.
+int pass_grid(long long total_planes)
+{
+    long long n = cu_count();
+    long long cap = total_planes / 12;
+    if (n > cap) n = cap;
+    n &= ~7LL;
+    return n < 8 ? 8 : (int)n;
+}
+
+template <class T, bool LIMIT, bool WRITE_VEL>
+int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hipStream_t st)
+{
+    mpdata::Geo g = geo_of(p);
+    const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
+    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL><<<pass_grid(total), mpdata::fused::kThreads, 0, st>>>(g, a);
+    return launch_status("fused corrective pass");
+}
+
+template <class T>
+int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, const T* cy, const T* cz,
+               const T* gm, void* ws, hipStream_t st)
+{
+    mpdata::Geo g = geo_of(p);
+    StepBufs<T> b = carve<T>(p, ws);
+    dim3 blk(64, 4, 1);
+    dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
+    T* first_out = p->iters == 1 ? psout : b.phi[0];
+    mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    if (int rc = launch_status("donor-cell pass")) return rc;
+
+    mpdata::fused::PassArgs<T> a;
+    a.psin = psin;
+    a.g = gm;
+    a.eps = p->eps > 0.0 ? p->eps : 1e-15;
+    a.tiles_x = (p->nx + mpdata::fused::kTileX - 1) / mpdata::fused::kTileX;
+    a.tiles_y = (p->ny + mpdata::fused::kTileY - 1) / mpdata::fused::kTileY;
+    a.u = cx;
+    a.v = cy;
+    a.w = cz;
+    const T* phi = b.phi[0];
+    int vsel = 0;
+    for (int m = 2; m <= p->iters; ++m) {
+        const bool last = m == p->iters;
+        T* nxt = last ? psout : (phi == b.phi[0] ? b.phi[1] : b.phi[0]);
+        a.phi = phi;
+        a.out = nxt;
+        a.ul = b.vel[vsel][0];
+        a.vl = b.vel[vsel][1];
+        a.wl = b.vel[vsel][2];
+        int rc;
+        if (p->limiter)
+            rc = last ? launch_pass<T, true, false>(p, a, st) : launch_pass<T, true, true>(p, a, st);
+        else
+            rc = last ? launch_pass<T, false, false>(p, a, st) : launch_pass<T, false, true>(p, a, st);
+        if (rc) return rc;
+        a.u = a.ul;
+        a.v = a.vl;
+        a.w = a.wl;
+        phi = nxt;
+        vsel ^= 1;
+    }
+    return ok();
+}
+
+bool use_stage_kernels()
+{
+    const char* e = getenv("MPDATA_KERNELS");
+    return e && strcmp(e, "stages") == 0;
+}
+
 int dispatch_step(const mpdata_problem* p, const void* psin, void* psout, const void* cx, const void* cy,
                   const void* cz, const void* gm, void* ws, hipStream_t st)
 {
-    if (p->dtype == MPDATA_F64)
-        return step_stages<double>(p, (const double*)psin, (double*)psout, (const double*)cx, (const double*)cy,
-                                   (const double*)cz, (const double*)gm, ws, st);
-    return step_stages<float>(p, (const float*)psin, (float*)psout, (const float*)cx, (const float*)cy,
-                              (const float*)cz, (const float*)gm, ws, st);
+    const bool stages = use_stage_kernels();
+    if (p->dtype == MPDATA_F64) {
+        auto f = stages ? step_stages<double> : step_fused<double>;
+        return f(p, (const double*)psin, (double*)psout, (const double*)cx, (const double*)cy, (const double*)cz,
+                 (const double*)gm, ws, st);
+    }
+    auto f = stages ? step_stages<float> : step_fused<float>;
+    return f(p, (const float*)psin, (float*)psout, (const float*)cx, (const float*)cy, (const float*)cz,
+             (const float*)gm, ws, st);
 }
 
 // ---------------------------------------------------------------------------

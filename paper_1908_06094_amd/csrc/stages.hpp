@@ -80,6 +80,10 @@ __global__ void __launch_bounds__(256) k_donor(Geo g, const T* __restrict__ phi,
     T dif[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        if (vel[a] == nullptr) {   // an absent velocity field is all zero
+            dif[a] = T(0) - T(0);
+            continue;
+        }
         int r[3] = {c.i, c.j, c.k}, l[3] = {c.i, c.j, c.k};
         r[a] += 1;
         l[a] -= 1;
