@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 METRIC = "grid-point updates/s per MPDATA step (FP64 vs FP32, HBM %); adjoint/forward time"
 
 
@@ -54,6 +54,59 @@ def bytes_per_cell_step(elem, with_cz=True):
     return elem * ((5 if with_cz else 4) + 1)
 
 
+def traffic_record(kernel_src_sha, dtype):
+    """Counter-derived HBM bytes per launch of the fused pass, if the committed
+    record was taken on the kernel source as it is now (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_fused_pass_{dtype}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_src_sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def kernel_source_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("fused.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1908_06094_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
+    """Roofline of the dominant kernel: the fused corrective pass (or, on the
+    per-stage path, all stage kernels of a step taken together)."""
+    from paper_1908_06094_amd import model
+
+    with_cz = True
+    if pass_n:
+        # passes 2..iters-1 also write their limited velocities
+        words = [model.pass_kernel_words(m < w.iters, with_cz) for m in range(2, w.iters + 1)]
+        bytes_per_launch = sum(words) / len(words) * elem * w.cells
+        avg_s = pass_ms * 1e-3 / pass_n
+        ops = model.corrective_pass_ops(w.limiter)
+        kernel = "fused corrective pass (k_pass)"
+        traffic = traffic_record(kernel_source_sha(), dtype)
+    else:
+        bytes_per_launch = bytes_per_cell_step(elem) * w.cells
+        avg_s = stage_ms * 1e-3 / max(stage_n, 1) if stage_n else ev_ms * 1e-3 / steps
+        ops = model.step_ops(w.iters, w.limiter)
+        kernel = "per-stage kernels of one step"
+        traffic = None
+    achieved = bytes_per_launch / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel, "bytes_per_launch": int(bytes_per_launch),
+            "avg_launch_us": round(avg_s * 1e6, 2)}
+    ops_s = ops.total * w.cells / avg_s
+    alu = {"bound": "alu", "achieved": round(ops_s / 1e12, 3), "peak": round(model.FP64_VALU_OPS_PEAK / 1e12, 2),
+           "unit": "T FP64 ops/s", "frac": round(ops_s / model.FP64_VALU_OPS_PEAK, 4),
+           "ops_per_cell": ops.total, "divisions_per_cell": ops.divisions}
+    return roof, alu
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +117,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run a plain device copy of one field (for counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -100,24 +155,33 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    mp.timing_enable(True)          # HIP events around every kernel launch, on the launch stream
     t0 = time.perf_counter()
     ev0.record(stream)
     mp.run(psi, cx, cy, cz, g, args.steps, **kw)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    mp.timing_enable(False)
     ev_ms = ev0.elapsed_time(ev1)
-    log(f"[bench] {args.steps} steps: wall {wall*1e3:.2f} ms, events {ev_ms:.2f} ms")
+    pass_ms, pass_n = mp.timing_read(mp.MPDATA_KERNEL_PASS)
+    donor_ms, donor_n = mp.timing_read(mp.MPDATA_KERNEL_DONOR)
+    stage_ms, stage_n = mp.timing_read(mp.MPDATA_KERNEL_STAGE)
+    log(f"[bench] {args.steps} steps: wall {wall*1e3:.2f} ms, events {ev_ms:.2f} ms; "
+        f"pass kernel {pass_n} x {pass_ms / max(pass_n, 1):.1f} ms, donor {donor_n} x "
+        f"{donor_ms / max(donor_n, 1):.1f} ms")
 
     ms_per_step = wall * 1e3 / args.steps
     updates = w.cells * args.steps / wall
-    step_bytes = bytes_per_cell_step(elem) * w.cells
-    ev_step_s = ev_ms * 1e-3 / args.steps
-    achieved = step_bytes / ev_step_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "whole step (all stage kernels)", "bytes_per_launch": step_bytes,
-            "avg_launch_us": round(ev_step_s * 1e6, 2)}
+    roof, alu = roofline(w, elem, args.dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, args.steps)
+
+    if args.copy_calibration:
+        src = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {src.numel() * elem} bytes")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -158,6 +222,12 @@ def main():
         "config": {"workload": w.name, "nx": w.shape[2], "ny": w.shape[1], "nz": w.shape[0],
                    "iters": w.iters, "limiter": w.limiter, "bc": list(w.bc), "parallelism": "single-gpu"},
         "roofline": roof,
+        "roofline_alu": alu,
+        "step": {"ms_per_step_events": round(ev_ms / args.steps, 4),
+                 "hbm_frac_step": round(bytes_per_cell_step(elem) * w.cells * args.steps / (ev_ms * 1e-3)
+                                        / 1e9 / HBM_PEAK_GBS, 4),
+                 "pass_launches": pass_n, "pass_ms_avg": round(pass_ms / max(pass_n, 1), 4),
+                 "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

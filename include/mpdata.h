@@ -100,6 +100,18 @@ int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g,
 /* Text of the last error on this thread ("" if none). */
 const char* mpdata_last_error(void);
 
+/* Kernel timing (diagnostics).  mpdata_timing_enable(1) clears the record and
+ * from then on brackets every launch of the library's kernels with HIP events
+ * on the launch stream; mpdata_timing_enable(0) stops recording.
+ * mpdata_timing_read() waits for the recorded events of one kernel kind and
+ * returns the summed elapsed milliseconds and the number of launches.  Kinds:
+ *   MPDATA_KERNEL_PASS   the fused corrective-pass kernel
+ *   MPDATA_KERNEL_DONOR  the donor-cell pass ahead of the fused passes
+ *   MPDATA_KERNEL_STAGE  the per-stage kernels (MPDATA_KERNELS=stages) */
+enum { MPDATA_KERNEL_PASS = 0, MPDATA_KERNEL_DONOR = 1, MPDATA_KERNEL_STAGE = 2 };
+int mpdata_timing_enable(int32_t on);
+int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

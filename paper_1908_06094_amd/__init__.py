@@ -14,6 +14,9 @@ from ._lib import (  # noqa: F401
     MPDATA_CLOSED,
     MPDATA_F32,
     MPDATA_F64,
+    MPDATA_KERNEL_DONOR,
+    MPDATA_KERNEL_PASS,
+    MPDATA_KERNEL_STAGE,
     MPDATA_OP_MASS,
     MPDATA_OP_RUN,
     MPDATA_OP_STEP,
@@ -26,5 +29,7 @@ from ._lib import (  # noqa: F401
     problem_for,
     run,
     step,
+    timing_enable,
+    timing_read,
     workspace_bytes,
 )

@@ -38,7 +38,12 @@ _SIGNATURES = {
     "mpdata_run": ([_pp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_mass": ([_pp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_last_error": ([], ctypes.c_char_p),
+    "mpdata_timing_enable": ([ctypes.c_int32], ctypes.c_int),
+    "mpdata_timing_read": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+                           ctypes.c_int),
 }
+
+MPDATA_KERNEL_PASS, MPDATA_KERNEL_DONOR, MPDATA_KERNEL_STAGE = 0, 1, 2
 
 
 def lib_path() -> str:
@@ -162,3 +167,16 @@ def mass(psi, g, *, bc=("periodic", "closed", "closed")) -> float:
     _check(lib().mpdata_mass(ctypes.byref(p), _ptr(psi), _ptr(g), ctypes.byref(out), _ptr(ws), ws.numel(),
                              ctypes.c_void_p(stream)))
     return out.value
+
+
+def timing_enable(on: bool = True) -> None:
+    """Start (clearing earlier records) or stop event timing of kernel launches."""
+    _check(lib().mpdata_timing_enable(1 if on else 0))
+
+
+def timing_read(kind: int):
+    """(total milliseconds, launches) of one kernel kind since timing_enable."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().mpdata_timing_read(kind, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

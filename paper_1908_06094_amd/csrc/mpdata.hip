@@ -9,7 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "mpdata.h"
 #include "common.hpp"
@@ -115,6 +118,50 @@ int launch_status(const char* what)
 }
 
 // ---------------------------------------------------------------------------
+// Kernel timing (diagnostics): when enabled, HIP events are recorded on the
+// launch stream around every kernel of a kind; reading sums their spans.
+// ---------------------------------------------------------------------------
+
+struct KernelTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[3];
+    std::vector<hipEvent_t> spare;
+};
+KernelTiming g_timing;
+
+hipEvent_t timing_event()
+{
+    hipEvent_t e = nullptr;
+    if (!g_timing.spare.empty()) {
+        e = g_timing.spare.back();
+        g_timing.spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Brackets one launch of `kind` on stream `st` with events (no-op when off).
+struct Timed {
+    int kind;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    Timed(int k, hipStream_t s) : kind(k), st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        if (g_timing.on && (e0 = timing_event())) hipEventRecord(e0, st);
+    }
+    ~Timed()
+    {
+        if (!e0) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        hipEvent_t e1 = timing_event();
+        if (e1 && hipEventRecord(e1, st) == hipSuccess) g_timing.spans[kind].push_back({e0, e1});
+    }
+};
+
+// ---------------------------------------------------------------------------
 // The pass driver (stage kernels)
 // ---------------------------------------------------------------------------
 
@@ -161,10 +208,14 @@ int step_stages(const mpdata_problem* p, const T* psin, T* psout, const T* cx, c
     dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
 
     T* first_out = p->iters == 1 ? psout : b.phi[0];
-    mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    {
+        Timed tm(MPDATA_KERNEL_STAGE, st);
+        mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    }
     if (int rc = launch_status("donor-cell pass")) return rc;
     if (p->iters == 1) return ok();
 
+    Timed tm(MPDATA_KERNEL_STAGE, st);   // the corrective passes' stage kernels as one span
     const T* prev[3] = {cx, cy, cz};
     const T* phi = b.phi[0];
     int vsel = 0;
@@ -228,6 +279,7 @@ int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hi
 {
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
+    Timed tm(MPDATA_KERNEL_PASS, st);
     mpdata::fused::k_pass<T, LIMIT, WRITE_VEL><<<pass_grid(total), mpdata::fused::kThreads, 0, st>>>(g, a);
     return launch_status("fused corrective pass");
 }
@@ -241,7 +293,10 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     dim3 blk(64, 4, 1);
     dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
     T* first_out = p->iters == 1 ? psout : b.phi[0];
-    mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    {
+        Timed tm(MPDATA_KERNEL_DONOR, st);
+        mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+    }
     if (int rc = launch_status("donor-cell pass")) return rc;
 
     mpdata::fused::PassArgs<T> a;
@@ -371,6 +426,38 @@ __global__ void __launch_bounds__(kMassThreads) k_mass_final(int nparts, double*
 extern "C" {
 
 const char* mpdata_last_error(void) { return g_err.c_str(); }
+
+int mpdata_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (auto& v : g_timing.spans) {
+        for (auto& pr : v) {
+            g_timing.spare.push_back(pr.first);
+            g_timing.spare.push_back(pr.second);
+        }
+        v.clear();
+    }
+    g_timing.on = on != 0;
+    return ok();
+}
+
+int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches)
+{
+    if (kind < 0 || kind > 2) return fail(MPDATA_EINVAL, "timing kind %d is not an MPDATA_KERNEL_* value", kind);
+    if (!total_ms || !launches) return fail(MPDATA_EINVAL, "output pointers must not be NULL");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double sum = 0.0;
+    for (auto& pr : g_timing.spans[kind]) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess) return fail(MPDATA_EDEVICE, "timing events: %s", hipGetErrorString(e));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)g_timing.spans[kind].size();
+    return ok();
+}
 
 size_t mpdata_workspace_bytes(const mpdata_problem* p, int32_t op, int32_t nsteps, int32_t checkpoint_every)
 {

@@ -196,3 +196,52 @@ def test_config3_full_size_one_step():
     got = t.cpu().numpy()
     assert _rel(got, want) <= TOL64
     assert got.min() >= 0.0
+
+
+# ---------------------------------------------------------------------------
+# FP32 storage and arithmetic (FP64 kept for beta's ratio and the mass sum)
+# ---------------------------------------------------------------------------
+
+# FP32 tolerance: the inputs are FP32-representable, so the error is the FP32
+# rounding of ~250 operations per pass accumulated over the steps; relative to
+# max|psi| it stays at a few hundred ulp of FP32 over 10 steps.
+TOL32 = 3e-5
+
+
+@pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6]])
+def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
+    torch = _torch()
+    mp = _mp()
+    _say(f"[parity-f32] path={kernels} shape={shape} bc={bc} iters={iters} limiter={lim}")
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=sum(shape) + iters, courant=0.8)
+    # FP32-representable inputs, so the comparison measures arithmetic precision only
+    psi, cx, cy, cz, g = (a.astype(np.float32).astype(np.float64) for a in (psi, cx, cy, cz, g))
+    p = oracle.RefProblem(shape[2], shape[1], shape[0], bc=bc, iters=iters, limiter=lim)
+    want = oracle.run(p, 10, psi, cx, cy, cz, g)
+    t = _dev(psi, torch.float32)
+    mp.run(t, *[_dev(a, torch.float32) for a in (cx, cy, cz, g)], 10, iters=iters, limiter=lim, bc=bc)
+    torch.cuda.synchronize()
+    got = t.double().cpu().numpy()
+    assert _rel(got, want) <= TOL32
+    if lim:
+        assert got.min() >= 0.0
+
+
+def test_fp32_config3_full_size():
+    """1024x512x80, 3 passes, limiter: FP32 vs the FP64 oracle at full size
+    (2 steps), positivity and FP64-accumulated mass."""
+    torch = _torch()
+    mp = _mp()
+    w = workloads.config3_fp32_inputs(workloads.config3())
+    _say(f"[parity-f32] {w.name} 2 steps at full size")
+    p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
+    want = oracle.run(p, 2, w.psi, w.cx, w.cy, w.cz, w.g)
+    t = _dev(w.psi, torch.float32)
+    args = [_dev(a, torch.float32) for a in (w.cx, w.cy, w.cz, w.g)]
+    m0 = mp.mass(t, args[3])
+    mp.run(t, *args, 2, iters=w.iters, limiter=w.limiter, bc=w.bc)
+    torch.cuda.synchronize()
+    got = t.double().cpu().numpy()
+    assert _rel(got, want) <= TOL32
+    assert got.min() >= 0.0
+    assert abs(mp.mass(t, args[3]) - m0) <= 1e-6 * m0

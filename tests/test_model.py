@@ -1,0 +1,39 @@
+"""The traffic model behind the roofline figures, pinned to the paper's own
+access counts (Section 6.1, Table 2) and to direct counting."""
+import json
+import os
+
+from paper_1908_06094_amd import model
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_table2_access_counts():
+    t = json.load(open(os.path.join(HERE, "golden", "table2_access_counts.json")))
+    for key in ("without_fusion", "with_fusion"):
+        row = t[key]
+        got = model.plane_accesses(row["edge_reads"], row["edge_writes"], row["node_reads"], row["node_writes"],
+                                   t["n_edges"], t["n_nodes"])
+        assert got == row["total"]
+    # the fused pattern moves more than 3x fewer words (the paper: "more than a factor 2")
+    assert t["without_fusion"]["total"] / t["with_fusion"]["total"] > 3.0
+
+
+def test_kernel_words():
+    assert model.STEP_WORDS == 6
+    assert model.donor_kernel_words() == 6
+    assert model.pass_kernel_words(False) == 7
+    assert model.pass_kernel_words(True) == 10
+
+
+def test_op_counts_consistent():
+    c = model.corrective_pass_ops(True)
+    u = model.corrective_pass_ops(False)
+    d = model.donor_pass_ops()
+    assert c.divisions == 3 * 5 + 2 + 1
+    assert u.divisions == 3 * 5 + 1
+    assert d.divisions == 1
+    s3 = model.step_ops(3, True)
+    assert s3.total == d.total + 2 * c.total
+    # the peak used for the ALU roofline: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz
+    assert abs(model.FP64_VALU_OPS_PEAK - 39.3216e12) < 1e9
