@@ -102,7 +102,8 @@ const char* mpdata_last_error(void);
 
 /* Kernel timing (diagnostics).  mpdata_timing_enable(1) clears the record and
  * from then on brackets every launch of the library's kernels with HIP events
- * on the launch stream; mpdata_timing_enable(0) stops recording.
+ * on the launch stream; mpdata_timing_enable(0) stops recording and keeps
+ * the record.
  * mpdata_timing_read() waits for the recorded events of one kernel kind and
  * returns the summed elapsed milliseconds and the number of launches.  Kinds:
  *   MPDATA_KERNEL_PASS   the fused corrective-pass kernel

@@ -225,9 +225,6 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
         const long long col = (long long)cj * geo.sy + ci;
         const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
-        const bool row_y = row <= kRows - 2;                 // forms its y face
-        const bool row_mid = row >= 1 && row <= kRows - 2;   // forms x and z faces and beta
-        const bool row_upd = row >= 1 && row <= kRows - 3;   // limits, fluxes, updates
 
         // plane loader: cell quantities through the halo rule, faces masked at walls
         auto load = [&](int k, Raw<T>& B) __attribute__((always_inline)) {
@@ -295,34 +292,25 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
             const T pz_dn = S.pz[dn][lane];
             const T vpz_dn = S.vpz[dn][lane];
             const T nphi_c = lane_next(C.phi);
+            const T gx_c = C.g + lane_next(C.g);
 
-            // Rows of the tile and what they must form (wave-uniform):
-            // row 0 only the y face (the inflow of row 1 reads it), rows
-            // 1..kRows-2 all faces and beta, rows 1..kRows-3 the limited
-            // velocities and fluxes; row kRows-1 only publishes its bounds.
-            T ux = zero, uy = zero, uz = zero;
-            if (row_mid) {
-                const T gx_c = C.g + lane_next(C.g);
-                // x face (i+1/2, j, k): transverse y then z
-                ux = antidiff_face(nphi_c - C.phi, C.px + eps,
-                                   px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
-                                   N.px - P.px, (N.px + P.px) + eps,
-                                   C.vpx + vpxdn_c, wsx, gx_c, C.u);
-                // z face (i, j, k+1/2): transverse x then y
-                const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
-                uz = antidiff_face(N.phi - C.phi, pz_c + eps,
-                                   pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
-                                   pz_up - pz_dn, (pz_up + pz_dn) + eps,
-                                   upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
-            }
-            if (row_y) {
-                // y face (i, j+1/2, k): transverse x then z
-                const T py_nx = lane_next(C.py), py_pv = lane_prev(C.py);
-                uy = antidiff_face(phiup_c - C.phi, C.py + eps,
-                                   py_nx - py_pv, (py_nx + py_pv) + eps,
-                                   N.py - P.py, (N.py + P.py) + eps,
-                                   C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
-            }
+            // x face (i+1/2, j, k): transverse y then z
+            const T ux = antidiff_face(nphi_c - C.phi, C.px + eps,
+                                       px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
+                                       N.px - P.px, (N.px + P.px) + eps,
+                                       C.vpx + vpxdn_c, wsx, gx_c, C.u);
+            // y face (i, j+1/2, k): transverse x then z
+            const T py_nx = lane_next(C.py), py_pv = lane_prev(C.py);
+            const T uy = antidiff_face(phiup_c - C.phi, C.py + eps,
+                                       py_nx - py_pv, (py_nx + py_pv) + eps,
+                                       N.py - P.py, (N.py + P.py) + eps,
+                                       C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
+            // z face (i, j, k+1/2): transverse x then y
+            const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
+            const T uz = antidiff_face(N.phi - C.phi, pz_c + eps,
+                                       pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
+                                       pz_up - pz_dn, (pz_up + pz_dn) + eps,
+                                       upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
 
             T ulx, uly, ulz;       // limited velocities: x, y at plane k; z at face k-1/2
             if (LIMIT) {
@@ -335,34 +323,29 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
                 lds_barrier();
 
                 // ---------------- phase 2: bounds, in/out, beta at plane k ----------------
-                T bup = zero, bdn = zero;
-                if (row_mid) {
-                    const T hi = fmx(fmx(C.mx, fmx(lane_next(C.mx), lane_prev(C.mx))),
-                                     fmx(fmx(S.mx[up][lane], S.mx[dn][lane]), fmx(P.mx, N.mx)));
-                    const T lo = fmn(fmn(C.mn, fmn(lane_next(C.mn), lane_prev(C.mn))),
-                                     fmn(fmn(S.mn[up][lane], S.mn[dn][lane]), fmn(P.mn, N.mn)));
-                    const T fpx = pos_f(ux) * C.phi;
-                    const T fmx_ = neg_f(ux) * nphi_c;
-                    const T fpz = pos_f(uz) * C.phi;
-                    const T fmz = neg_f(uz) * N.phi;
-                    const T fpz_l = pos_f(uz_p) * P.phi;
-                    const T fmz_l = neg_f(uz_p) * C.phi;
-                    const T fin = ((lane_prev(fpx) - fmx_) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
-                    const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
-                    beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
-                    S.bup[row][lane] = bup;
-                    S.bdn[row][lane] = bdn;
-                }
+                const T hi = fmx(fmx(C.mx, fmx(lane_next(C.mx), lane_prev(C.mx))),
+                                 fmx(fmx(S.mx[up][lane], S.mx[dn][lane]), fmx(P.mx, N.mx)));
+                const T lo = fmn(fmn(C.mn, fmn(lane_next(C.mn), lane_prev(C.mn))),
+                                 fmn(fmn(S.mn[up][lane], S.mn[dn][lane]), fmn(P.mn, N.mn)));
+                const T fpx = pos_f(ux) * C.phi;
+                const T fmx_ = neg_f(ux) * nphi_c;
+                const T fpz = pos_f(uz) * C.phi;
+                const T fmz = neg_f(uz) * N.phi;
+                const T fpz_l = pos_f(uz_p) * P.phi;
+                const T fmz_l = neg_f(uz_p) * C.phi;
+                const T fin = ((lane_prev(fpx) - fmx_) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
+                const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
+                T bup, bdn;
+                beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
+                S.bup[row][lane] = bup;
+                S.bdn[row][lane] = bdn;
                 lds_barrier();
 
                 // ---------------- phase 3a: limited velocities ----------------
-                ulx = uly = ulz = zero;
-                if (row_upd) {
-                    const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
-                    ulx = pos_f(ux) * min3(T(1), bdn, lane_next(bup)) + neg_f(ux) * min3(T(1), bup, lane_next(bdn));
-                    uly = pos_f(uy) * min3(T(1), bdn, bup_up) + neg_f(uy) * min3(T(1), bup, bdn_up);
-                    ulz = pos_f(uz_p) * min3(T(1), bdn_p, bup) + neg_f(uz_p) * min3(T(1), bup_p, bdn);
-                }
+                const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
+                ulx = pos_f(ux) * min3(T(1), bdn, lane_next(bup)) + neg_f(ux) * min3(T(1), bup, lane_next(bdn));
+                uly = pos_f(uy) * min3(T(1), bdn, bup_up) + neg_f(uy) * min3(T(1), bup, bdn_up);
+                ulz = pos_f(uz_p) * min3(T(1), bdn_p, bup) + neg_f(uz_p) * min3(T(1), bup_p, bdn);
                 bup_p = bup;
                 bdn_p = bdn;
             } else {
@@ -373,15 +356,12 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
 
             // ---------------- phase 3b: donor-cell update of plane k-1 ----------------
             const int par = t & 1;
-            T fx_c = zero, fy_c = zero, fz_h = zero, fy_p_dn = zero, fx_p_l = zero;
-            if (row_upd) {
-                fx_c = pos_f(ulx) * C.phi + neg_f(ulx) * nphi_c;
-                fy_c = pos_f(uly) * C.phi + neg_f(uly) * phiup_c;
-                S.fy[par][row][lane] = fy_c;
-                fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
-                fy_p_dn = S.fy[par ^ 1][dn][lane];
-                fx_p_l = lane_prev(fx_p);          // whole wave active: DPP sources are live
-            }
+            const T fx_c = pos_f(ulx) * C.phi + neg_f(ulx) * nphi_c;
+            const T fy_c = pos_f(uly) * C.phi + neg_f(uly) * phiup_c;
+            S.fy[par][row][lane] = fy_c;
+            const T fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
+            const T fy_p_dn = S.fy[par ^ 1][dn][lane];
+            const T fx_p_l = lane_prev(fx_p);      // every lane: DPP needs its source lanes active
             const int ko = t - 2;                  // plane k-1
             if (writer && ko >= kb && ko < ke) {
                 const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);

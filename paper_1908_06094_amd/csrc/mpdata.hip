@@ -430,12 +430,14 @@ const char* mpdata_last_error(void) { return g_err.c_str(); }
 int mpdata_timing_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    for (auto& v : g_timing.spans) {
-        for (auto& pr : v) {
-            g_timing.spare.push_back(pr.first);
-            g_timing.spare.push_back(pr.second);
+    if (on) {   // a new record; turning timing off keeps the record for reading
+        for (auto& v : g_timing.spans) {
+            for (auto& pr : v) {
+                g_timing.spare.push_back(pr.first);
+                g_timing.spare.push_back(pr.second);
+            }
+            v.clear();
         }
-        v.clear();
     }
     g_timing.on = on != 0;
     return ok();
