@@ -461,3 +461,385 @@ int ref_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Reverse (adjoint) sweep                                            */
+/*                                                                    */
+/* Each stage's adjoint is a scatter loop: every forward output       */
+/* distributes lam(output) * d(output)/d(input) to the inputs it      */
+/* read, through the same halo rules the forward stage used.  At the  */
+/* kinks the derivative follows the branch taken:                     */
+/*   [c]+ has derivative [c > 0], [c]- has [c < 0], |c| has sign(c)   */
+/*   with sign(0) = 0;                                                */
+/*   min(1, min(a, b)) routes to the first minimal entry of (1, a, b) */
+/*   (nothing when it is the constant 1);                             */
+/*   the bounds route to the first extremal entry of the list         */
+/*   psi^n at (self, -x, +x, -y, +y, -z, +z), then phi in the same    */
+/*   order.                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Linear index of a cell after the halo rule. */
+static int64_t cell_lin(const ref_problem* p, const int c[3])
+{
+    return lin(p, cell_index(p, 0, c[0]), cell_index(p, 1, c[1]), cell_index(p, 2, c[2]));
+}
+
+/* Linear index of face c[axis]+1/2 (the same rule as facev), or -1 where the
+ * face is a closed wall (the value read there is the constant 0). */
+static int64_t face_lin(const ref_problem* p, int axis, const int c[3])
+{
+    int d[3];
+    for (int b = 0; b < 3; ++b)
+        d[b] = (b == axis) ? c[b] : cell_index(p, b, c[b]);
+    int n = extent(p, axis);
+    if (p->bc[axis] == REF_CLOSED) {
+        if (d[axis] <= -1 || d[axis] >= n - 1) return -1;
+    } else {
+        d[axis] = ((d[axis] % n) + n) % n;
+    }
+    return lin(p, d[0], d[1], d[2]);
+}
+
+static double step_fn(double c) { return c > 0.0 ? 1.0 : 0.0; }     /* d[c]+/dc */
+static double stepn_fn(double c) { return c < 0.0 ? 1.0 : 0.0; }    /* d[c]-/dc */
+static double sgn(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? -1.0 : 0.0); }
+
+/* Adjoint of ref_donor: lout -> lphi (+=), lvel[a] (+=). */
+static void adj_donor(const ref_problem* p, const double* phi, const double* const vel[3],
+                      const double* g, const double* lout, double* lphi, double* const lvel[3])
+{
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                int64_t q = lin(p, i, j, k);
+                lphi[q] += lout[q];   /* out = phi - div / G */
+                for (int a = 0; a < 3; ++a) {
+                    int64_t fi = face_lin(p, a, c);
+                    if (fi < 0) continue;          /* wall: the flux is the constant 0 */
+                    int r[3] = {i, j, k};
+                    r[a] += 1;
+                    int64_t qr = cell_lin(p, r);
+                    /* the flux through face c+1/2 leaves c and enters r */
+                    double lamf = lout[qr] / g[qr] - lout[q] / g[q];
+                    double v = vel[a][fi];
+                    lphi[q] += pos(v) * lamf;
+                    lphi[qr] += neg(v) * lamf;
+                    lvel[a][fi] += (step_fn(v) * phi[q] + stepn_fn(v) * phi[qr]) * lamf;
+                }
+            }
+}
+
+/* Index (0, 1 or 2) of the first minimal entry of (1, x, y). */
+static int first_min3(double x, double y)
+{
+    double m = dmin(1.0, dmin(x, y));
+    if (1.0 == m) return 0;
+    if (x == m) return 1;
+    return 2;
+}
+
+/* Adjoint of ref_limit: lvl -> lut (+=), lbup (+=), lbdn (+=). */
+static void adj_limit(const ref_problem* p, const double* const ut[3], const double* bup,
+                      const double* bdn, const double* const lvl[3], double* const lut[3],
+                      double* lbup, double* lbdn)
+{
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    int L[3] = {i, j, k}, R[3] = {i, j, k};
+                    R[a] += 1;
+                    int64_t q = lin(p, i, j, k);
+                    if (is_wall_face(p, a, L[a])) continue;
+                    int64_t qr = cell_lin(p, R);
+                    double U = ut[a][q];
+                    double lam = lvl[a][q];
+                    double up = dmin(1.0, dmin(bdn[q], bup[qr]));
+                    double dn = dmin(1.0, dmin(bup[q], bdn[qr]));
+                    lut[a][q] += lam * (step_fn(U) * up + stepn_fn(U) * dn);
+                    if (U > 0.0) {
+                        int w = first_min3(bdn[q], bup[qr]);
+                        if (w == 1) lbdn[q] += lam * U;
+                        if (w == 2) lbup[qr] += lam * U;
+                    } else if (U < 0.0) {
+                        int w = first_min3(bup[q], bdn[qr]);
+                        if (w == 1) lbup[q] += lam * U;
+                        if (w == 2) lbdn[qr] += lam * U;
+                    }
+                }
+}
+
+/* Adjoint of ref_beta: (lbup, lbdn) -> lphi (+=), lut (+=), lmx (+=), lmn (+=). */
+static void adj_beta(const ref_problem* p, const double* phi, const double* const ut[3],
+                     const double* mx, const double* mn, const double* g, const double* lbup,
+                     const double* lbdn, double* lphi, double* const lut[3], double* lmx, double* lmn)
+{
+    const double eps = eps_of(p);
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int c[3] = {i, j, k};
+                int64_t q = lin(p, i, j, k);
+                /* recompute in and out as ref_beta does */
+                double fin[3], fout[3];
+                int64_t fl[3], fr[3], ql[3], qr[3];
+                double vl[3], vr[3];
+                for (int a = 0; a < 3; ++a) {
+                    int l[3] = {i, j, k}, r[3] = {i, j, k};
+                    l[a] -= 1;
+                    r[a] += 1;
+                    fr[a] = face_lin(p, a, c);
+                    fl[a] = face_lin(p, a, l);
+                    vr[a] = fr[a] < 0 ? 0.0 : ut[a][fr[a]];
+                    vl[a] = fl[a] < 0 ? 0.0 : ut[a][fl[a]];
+                    ql[a] = cell_lin(p, l);
+                    qr[a] = cell_lin(p, r);
+                    fin[a] = pos(vl[a]) * phi[ql[a]] - neg(vr[a]) * phi[qr[a]];
+                    fout[a] = pos(vr[a]) * phi[q] - neg(vl[a]) * phi[q];
+                }
+                double in = ((fin[0] + fin[1]) + fin[2]);
+                double out = ((fout[0] + fout[1]) + fout[2]);
+                double din = in + eps, dout = out + eps;
+                double bu = ((mx[q] - phi[q]) * g[q]) / din;
+                double bd = ((phi[q] - mn[q]) * g[q]) / dout;
+                double gu = lbup[q], gd = lbdn[q];
+                lmx[q] += gu * g[q] / din;
+                lmn[q] -= gd * g[q] / dout;
+                lphi[q] += -gu * g[q] / din + gd * g[q] / dout;
+                double lin_ = -gu * bu / din;
+                double lout_ = -gd * bd / dout;
+                for (int a = 0; a < 3; ++a) {
+                    /* in = sum [vl]+ phi(l) - [vr]- phi(r) */
+                    lphi[ql[a]] += lin_ * pos(vl[a]);
+                    lphi[qr[a]] -= lin_ * neg(vr[a]);
+                    if (fl[a] >= 0) lut[a][fl[a]] += lin_ * step_fn(vl[a]) * phi[ql[a]];
+                    if (fr[a] >= 0) lut[a][fr[a]] -= lin_ * stepn_fn(vr[a]) * phi[qr[a]];
+                    /* out = sum [vr]+ phi(c) - [vl]- phi(c) */
+                    lphi[q] += lout_ * (pos(vr[a]) - neg(vl[a]));
+                    if (fr[a] >= 0) lut[a][fr[a]] += lout_ * step_fn(vr[a]) * phi[q];
+                    if (fl[a] >= 0) lut[a][fl[a]] -= lout_ * stepn_fn(vl[a]) * phi[q];
+                }
+            }
+}
+
+/* Adjoint of ref_bounds: (lmx, lmn) -> lpsin (+=), lphi (+=). */
+static void adj_bounds(const ref_problem* p, const double* psin, const double* phi, const double* lmx,
+                       const double* lmn, double* lpsin, double* lphi)
+{
+    static const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                int64_t q = lin(p, i, j, k);
+                int64_t idx[14];
+                double val[14];
+                for (int f = 0; f < 2; ++f)
+                    for (int o = 0; o < 7; ++o) {
+                        int d[3] = {i + off[o][0], j + off[o][1], k + off[o][2]};
+                        idx[f * 7 + o] = cell_lin(p, d);
+                        val[f * 7 + o] = (f == 0 ? psin : phi)[idx[f * 7 + o]];
+                    }
+                int am = 0, an = 0;
+                for (int e = 1; e < 14; ++e) {
+                    if (val[e] > val[am]) am = e;
+                    if (val[e] < val[an]) an = e;
+                }
+                (am < 7 ? lpsin : lphi)[idx[am]] += lmx[q];
+                (an < 7 ? lpsin : lphi)[idx[an]] += lmn[q];
+            }
+}
+
+/* Adjoint of ref_antidiff: lut -> lphi (+=), lvel (+=). */
+static void adj_antidiff(const ref_problem* p, const double* phi, const double* const vel[3],
+                         const double* g, const double* const lut[3], double* lphi, double* const lvel[3])
+{
+    const double eps = eps_of(p);
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    int L[3] = {i, j, k};
+                    int64_t q = lin(p, i, j, k);
+                    if (is_wall_face(p, a, L[a])) continue;
+                    double lam = lut[a][q];
+                    int R[3] = {i, j, k};
+                    R[a] += 1;
+                    int tr[2], nt = 0;
+                    for (int b = 0; b < 3; ++b)
+                        if (b != a) tr[nt++] = b;
+                    int64_t qL = cell_lin(p, L), qR = cell_lin(p, R);
+                    double pL = phi[qL], pR = phi[qR];
+                    double D0 = (pR + pL) + eps;
+                    double A = (pR - pL) / D0;
+                    double B[2], Vb[2], Dt[2], Sp[2], Sm[2];
+                    int64_t qLp[2], qRp[2], qLm[2], qRm[2], f4[2][4];
+                    for (int s = 0; s < 2; ++s) {
+                        int t = tr[s];
+                        int Lp[3] = {L[0], L[1], L[2]}, Rp[3] = {R[0], R[1], R[2]};
+                        int Lm[3] = {L[0], L[1], L[2]}, Rm[3] = {R[0], R[1], R[2]};
+                        Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
+                        qLp[s] = cell_lin(p, Lp); qRp[s] = cell_lin(p, Rp);
+                        qLm[s] = cell_lin(p, Lm); qRm[s] = cell_lin(p, Rm);
+                        Sp[s] = phi[qRp[s]] + phi[qLp[s]];
+                        Sm[s] = phi[qRm[s]] + phi[qLm[s]];
+                        Dt[s] = (Sp[s] + Sm[s]) + eps;
+                        B[s] = 0.5 * ((Sp[s] - Sm[s]) / Dt[s]);
+                        f4[s][0] = face_lin(p, t, L);
+                        f4[s][1] = face_lin(p, t, R);
+                        f4[s][2] = face_lin(p, t, Lm);
+                        f4[s][3] = face_lin(p, t, Rm);
+                        double vs = 0.0;
+                        double fv[4];
+                        for (int e = 0; e < 4; ++e) fv[e] = f4[s][e] < 0 ? 0.0 : vel[t][f4[s][e]];
+                        vs = (fv[0] + fv[1]) + (fv[2] + fv[3]);
+                        Vb[s] = 0.25 * vs;
+                    }
+                    double Gf = 0.5 * (g[qL] + g[qR]);
+                    double U = vel[a][q];
+                    double S = (Vb[0] * B[0]) + (Vb[1] * B[1]);
+                    /* U~ = (|U| - U^2/Gf) A - (U/Gf) S */
+                    double dU = (sgn(U) - 2.0 * U / Gf) * A - S / Gf;
+                    double dA = fabs(U) - (U * U) / Gf;
+                    double dS = -U / Gf;
+                    lvel[a][q] += lam * dU;
+                    double gA = lam * dA;
+                    lphi[qR] += gA * (2.0 * pL + eps) / (D0 * D0);
+                    lphi[qL] -= gA * (2.0 * pR + eps) / (D0 * D0);
+                    for (int s = 0; s < 2; ++s) {
+                        double gB = lam * dS * Vb[s];
+                        double gV = lam * dS * B[s];
+                        double dSp = 0.5 * (2.0 * Sm[s] + eps) / (Dt[s] * Dt[s]);
+                        double dSm = -0.5 * (2.0 * Sp[s] + eps) / (Dt[s] * Dt[s]);
+                        lphi[qRp[s]] += gB * dSp;
+                        lphi[qLp[s]] += gB * dSp;
+                        lphi[qRm[s]] += gB * dSm;
+                        lphi[qLm[s]] += gB * dSm;
+                        for (int e = 0; e < 4; ++e)
+                            if (f4[s][e] >= 0) lvel[tr[s]][f4[s][e]] += 0.25 * gV;
+                    }
+                }
+}
+
+int ref_adjoint(const ref_problem* p, int32_t nsteps, const double* psi0,
+                const double* cx, const double* cy, const double* cz,
+                const double* g, const double* seed, double* dpsi0,
+                double* dcx, double* dcy, double* dcz)
+{
+    if (!valid(p) || nsteps < 0 || !psi0 || !cx || !cy || !g || !seed || !dpsi0 || !dcx || !dcy) return -1;
+    const int64_t n = ncells(p);
+    const size_t bytes = sizeof(double) * (size_t)n;
+    const int M = p->iters;
+    double* zero = (double*)calloc((size_t)n, sizeof(double));
+    double* dcz_local = (double*)calloc((size_t)n, sizeof(double));
+    /* states psi^0..psi^{nsteps-1}; per pass m: phi_m, U~_m (3), V_m (3), mx, mn, bup, bdn */
+    double* states = (double*)malloc(bytes * (size_t)(nsteps > 0 ? nsteps : 1));
+    double* phis = (double*)malloc(bytes * (size_t)(M + 1));
+    double* uts = (double*)malloc(bytes * 3 * (size_t)(M + 1));
+    double* vls = (double*)malloc(bytes * 3 * (size_t)(M + 1));
+    double* bnd = (double*)malloc(bytes * 4 * (size_t)(M + 1));
+    double* lam = (double*)malloc(bytes * 12);
+    if (!zero || !dcz_local || !states || !phis || !uts || !vls || !bnd || !lam) {
+        free(zero); free(dcz_local); free(states); free(phis); free(uts); free(vls); free(bnd); free(lam);
+        return -1;
+    }
+    if (!cz) cz = zero;
+    double* dC[3] = {dcx, dcy, dcz ? dcz : dcz_local};
+    memset(dcx, 0, bytes);
+    memset(dcy, 0, bytes);
+    memset(dC[2], 0, bytes);
+
+    /* forward sweep storing the step states */
+    if (nsteps > 0) memcpy(states, psi0, bytes);
+    for (int s = 1; s < nsteps; ++s)
+        ref_step(p, states + (size_t)(s - 1) * n, states + (size_t)s * n, cx, cy, cz, g);
+
+    double* lcur = lam;              /* adjoint of the current iterate  */
+    double* lprev = lam + n;         /* adjoint of the previous iterate */
+    double* lpsin = lam + 2 * n;     /* adjoint of psi^n                */
+    double* lv[3] = {lam + 3 * n, lam + 4 * n, lam + 5 * n};     /* of V_m     */
+    double* lvp[3] = {lam + 6 * n, lam + 7 * n, lam + 8 * n};    /* of V_{m-1} */
+    double* lb = lam + 9 * n;        /* of beta_up, beta_dn (2 fields)  */
+    double* lmxmn = lam + 11 * n;    /* of mx (lmn reuses lb after beta) */
+    double* lut_[3] = {NULL, NULL, NULL};
+    double* lutbuf = (double*)malloc(bytes * 5);
+    if (!lutbuf) {
+        free(zero); free(dcz_local); free(states); free(phis); free(uts); free(vls); free(bnd); free(lam);
+        return -1;
+    }
+    double* lmn = lutbuf + 3 * n;
+    double* lbdn = lutbuf + 4 * n;
+    for (int a = 0; a < 3; ++a) lut_[a] = lutbuf + (size_t)a * n;
+
+    memcpy(lcur, seed, bytes);
+    const double* C3[3] = {cx, cy, cz};
+    for (int s = nsteps - 1; s >= 0; --s) {
+        const double* psin = states + (size_t)s * n;
+        /* recompute the step's intermediates, pass by pass */
+        ref_donor(p, psin, cx, cy, cz, g, phis + (size_t)1 * n);
+        for (int m = 2; m <= M; ++m) {
+            const double* prev[3];
+            for (int a = 0; a < 3; ++a)
+                prev[a] = (m == 2) ? C3[a] : vls + ((size_t)3 * (m - 1) + a) * n;
+            double* U3[3] = {uts + ((size_t)3 * m) * n, uts + ((size_t)3 * m + 1) * n, uts + ((size_t)3 * m + 2) * n};
+            double* V3[3] = {vls + ((size_t)3 * m) * n, vls + ((size_t)3 * m + 1) * n, vls + ((size_t)3 * m + 2) * n};
+            double* B4 = bnd + (size_t)4 * m * n;
+            const double* ph = phis + (size_t)(m - 1) * n;
+            ref_antidiff(p, ph, prev[0], prev[1], prev[2], g, U3[0], U3[1], U3[2]);
+            if (p->limiter) {
+                ref_bounds(p, psin, ph, B4, B4 + n);
+                ref_beta(p, ph, U3[0], U3[1], U3[2], B4, B4 + n, g, B4 + 2 * n, B4 + 3 * n);
+                ref_limit(p, U3[0], U3[1], U3[2], B4 + 2 * n, B4 + 3 * n, V3[0], V3[1], V3[2]);
+            } else {
+                for (int a = 0; a < 3; ++a) memcpy(V3[a], U3[a], bytes);
+            }
+            ref_donor(p, ph, V3[0], V3[1], V3[2], g, phis + (size_t)m * n);
+        }
+
+        /* reverse through the passes */
+        memset(lpsin, 0, bytes);
+        for (int a = 0; a < 3; ++a) memset(lv[a], 0, bytes);
+        for (int m = M; m >= 2; --m) {
+            const double* ph = phis + (size_t)(m - 1) * n;
+            const double* V3[3] = {vls + ((size_t)3 * m) * n, vls + ((size_t)3 * m + 1) * n, vls + ((size_t)3 * m + 2) * n};
+            const double* U3[3] = {uts + ((size_t)3 * m) * n, uts + ((size_t)3 * m + 1) * n, uts + ((size_t)3 * m + 2) * n};
+            const double* B4 = bnd + (size_t)4 * m * n;
+            const double* prev[3];
+            for (int a = 0; a < 3; ++a)
+                prev[a] = (m == 2) ? C3[a] : vls + ((size_t)3 * (m - 1) + a) * n;
+            memset(lprev, 0, bytes);
+            for (int a = 0; a < 3; ++a) memset(lvp[a], 0, bytes);
+            /* phi_m = donor(phi_{m-1}, V_m): lv already holds the A-adjoint part from pass m+1 */
+            adj_donor(p, ph, V3, g, lcur, lprev, lv);
+            if (p->limiter) {
+                for (int a = 0; a < 3; ++a) memset(lut_[a], 0, bytes);
+                memset(lb, 0, bytes);
+                memset(lbdn, 0, bytes);
+                memset(lmxmn, 0, bytes);
+                memset(lmn, 0, bytes);
+                adj_limit(p, U3, B4 + 2 * n, B4 + 3 * n, (const double* const*)lv, lut_, lb, lbdn);
+                adj_beta(p, ph, U3, B4, B4 + n, g, lb, lbdn, lprev, lut_, lmxmn, lmn);
+                adj_bounds(p, psin, ph, lmxmn, lmn, lpsin, lprev);
+            } else {
+                for (int a = 0; a < 3; ++a) memcpy(lut_[a], lv[a], bytes);
+            }
+            double* const* lvtarget = (m == 2) ? dC : lvp;
+            adj_antidiff(p, ph, prev, g, (const double* const*)lut_, lprev, lvtarget);
+            /* move to pass m-1 */
+            double* t = lcur;
+            lcur = lprev;
+            lprev = t;
+            for (int a = 0; a < 3; ++a) {
+                double* tt = lv[a];
+                lv[a] = lvp[a];
+                lvp[a] = tt;
+            }
+        }
+        /* pass 1: phi_1 = donor(psi^n, C) */
+        adj_donor(p, psin, C3, g, lcur, lpsin, dC);
+        memcpy(lcur, lpsin, bytes);
+    }
+    memcpy(dpsi0, lcur, bytes);
+    free(lutbuf); free(zero); free(dcz_local); free(states); free(phis); free(uts); free(vls); free(bnd); free(lam);
+    return 0;
+}

@@ -83,6 +83,17 @@ int ref_run(const ref_problem* p, int32_t nsteps, double* psi,
 int ref_mass(const ref_problem* p, const double* psi, const double* g,
              double* out);
 
+/* Reverse (adjoint) sweep of ref_run.  Given the seed lam = dJ/dpsi_T of a
+ * cost J(psi_T), returns dJ/dpsi0 and dJ/d(cx, cy, cz) (dcz may be NULL).
+ * Every step's intermediates are recomputed from stored step states; at the
+ * kinks of max/min the derivative follows the argument taken, the first
+ * extremal one in a fixed order (see mpdata_ref.c).  Plain scatter loops,
+ * serial. */
+int ref_adjoint(const ref_problem* p, int32_t nsteps, const double* psi0,
+                const double* cx, const double* cy, const double* cz,
+                const double* g, const double* seed, double* dpsi0,
+                double* dcx, double* dcy, double* dcz);
+
 /* Threads the oracle's parallel loops use (OpenMP). */
 int ref_num_threads(void);
 

@@ -89,6 +89,8 @@ def _load():
         lib.ref_run.restype = ctypes.c_int
         lib.ref_mass.argtypes = [pp, _P, _P, _P]
         lib.ref_mass.restype = ctypes.c_int
+        lib.ref_adjoint.argtypes = [pp, ctypes.c_int32] + [_P] * 10
+        lib.ref_adjoint.restype = ctypes.c_int
         lib.ref_num_threads.argtypes = []
         lib.ref_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -185,5 +187,12 @@ def num_threads() -> int:
     return int(_load().ref_num_threads())
 
 
-def adjoint(*args, **kwargs):  # pragma: no cover - filled in with the reverse sweep
-    raise NotImplementedError("the oracle's reverse sweep is not built yet")
+def adjoint(p: RefProblem, nsteps: int, psi0, cx, cy, cz, g, seed):
+    """Reverse sweep: (dJ/dpsi0, dJ/dcx, dJ/dcy, dJ/dcz) for the seed dJ/dpsi_T."""
+    s = p.shape
+    psi0, cx, cy, g, seed = (_arr(x, s) for x in (psi0, cx, cy, g, seed))
+    cz = None if cz is None else _arr(cz, s)
+    out = [np.empty(s) for _ in range(4)]
+    _call("ref_adjoint", ctypes.byref(p.c()), int(nsteps), _ptr(psi0), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
+          _ptr(seed), *[_ptr(o) for o in out])
+    return tuple(out)
