@@ -107,6 +107,42 @@ def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
     return roof, alu
 
 
+def time_adjoint(mp, torch, dev, steps=20, checkpoint_every=5, reps=3):
+    """Adjoint/forward time on the 256x128x60 lat-lon workload (FP64, 2 passes,
+    limiter, solid-body winds): mpdata_adjoint over `steps` steps with
+    checkpoints every `checkpoint_every` steps (its forward recomputation
+    included) against `steps` forward steps."""
+    import numpy as np
+
+    import workloads
+
+    w = workloads.config2()
+    wt = torch.from_numpy(workloads.config5_weights(w.shape)).to(dev)
+    psi0, cx, cy, cz, g = (torch.from_numpy(a).to(dev) for a in (w.psi, w.cx, w.cy, w.cz, w.g))
+    kw = dict(iters=2, limiter=True, bc=w.bc)
+    out = psi0.clone()
+    mp.run(out, cx, cy, cz, g, steps, **kw)
+    seed = 2 * wt * out
+    mp.adjoint(psi0, cx, cy, cz, g, seed, steps, checkpoint_every=checkpoint_every, **kw)   # warm-up
+    torch.cuda.synchronize()
+    fwd, adj = [], []
+    for _ in range(reps):
+        t = psi0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mp.run(t, cx, cy, cz, g, steps, **kw)
+        torch.cuda.synchronize()
+        fwd.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        mp.adjoint(psi0, cx, cy, cz, g, seed, steps, checkpoint_every=checkpoint_every, **kw)
+        torch.cuda.synchronize()
+        adj.append(time.perf_counter() - t0)
+    f, a = float(np.median(fwd)), float(np.median(adj))
+    log(f"[bench] adjoint: forward {f*1e3:.2f} ms, adjoint {a*1e3:.2f} ms for {steps} steps")
+    return {"workload": f"{w.name} FP64, {steps} steps, checkpoint every {checkpoint_every}",
+            "forward_ms": round(f * 1e3, 3), "adjoint_ms": round(a * 1e3, 3), "ratio": round(a / f, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward timing on the 256x128x60 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain device copy of one field (for counter calibration)")
     args = ap.parse_args()
@@ -175,6 +213,10 @@ def main():
     updates = w.cells * args.steps / wall
     roof, alu = roofline(w, elem, args.dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, args.steps)
 
+    adjoint = None
+    if not args.no_adjoint and args.dtype == "f64":
+        adjoint = time_adjoint(mp, torch, dev)
+
     if args.copy_calibration:
         src = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -229,6 +271,7 @@ def main():
                  "pass_launches": pass_n, "pass_ms_avg": round(pass_ms / max(pass_n, 1), 4),
                  "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
         "cpu_baseline": cpu,
+        "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
 

@@ -91,6 +91,26 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
                const void* cx, const void* cy, const void* cz, const void* g,
                void* ws, size_t ws_bytes, void* stream);
 
+/* Adjoint (reverse mode) of mpdata_run, FP64 only.  For a cost J(psi_T) of
+ * the state after nsteps steps, takes the seed dJ_dpsiT = dJ/dpsi_T and
+ * returns dJ/dpsi0 and dJ/d(cx, cy, cz) (dJ_dcz may be NULL to skip it; the
+ * closed-wall slots of the gradients are 0).  The forward trajectory is
+ * recomputed from psi0: states are kept every checkpoint_every steps (0 =
+ * only psi0) and each segment is recomputed before its reverse sweep.  At
+ * the kinks of max/min the derivative follows the branch the forward step
+ * took ([c]+ differentiates to [c > 0], |c| to sign(c) with sign(0) = 0,
+ * min(1, min(a, b)) to its first minimal entry, the limiter bounds to their
+ * first extremal entry).  psiT_out (nullable) receives psi_T.  No atomics:
+ * the result is bitwise reproducible.  ws: at least the MPDATA_OP_ADJOINT
+ * size for the same nsteps and checkpoint_every.  The MPDATA iterations and
+ * limiter this differentiates are those of mpdata_step (paper, Section 5,
+ * and the scheme's literature); the paper itself has no adjoint. */
+int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_every,
+                   const void* psi0, const void* cx, const void* cy, const void* cz,
+                   const void* g, const void* dJ_dpsiT, void* dJ_dpsi0, void* dJ_dcx,
+                   void* dJ_dcy, void* dJ_dcz, void* psiT_out, void* ws, size_t ws_bytes,
+                   void* stream);
+
 /* Mass sum(G * psi) accumulated in FP64 (compensated) for either dtype,
  * written to *host_out.  Synchronises `stream`.  ws: at least the
  * MPDATA_OP_MASS size. */

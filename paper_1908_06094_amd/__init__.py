@@ -17,11 +17,14 @@ from ._lib import (  # noqa: F401
     MPDATA_KERNEL_DONOR,
     MPDATA_KERNEL_PASS,
     MPDATA_KERNEL_STAGE,
+    MPDATA_OP_ADJOINT,
     MPDATA_OP_MASS,
     MPDATA_OP_RUN,
     MPDATA_OP_STEP,
     MPDATA_PERIODIC,
     MpdataError,
+    adjoint,
+    mpdata_function,
     Problem,
     lib,
     lib_path,
@@ -33,3 +36,9 @@ from ._lib import (  # noqa: F401
     timing_read,
     workspace_bytes,
 )
+
+
+def __getattr__(name):
+    if name == "MPDATAFunction":
+        return mpdata_function()
+    raise AttributeError(name)

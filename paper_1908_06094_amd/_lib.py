@@ -37,6 +37,8 @@ _SIGNATURES = {
     "mpdata_step": ([_pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_run": ([_pp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_mass": ([_pp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "mpdata_adjoint": ([_pp, ctypes.c_int32, ctypes.c_int32] + [_vp] * 11 + [_vp, ctypes.c_size_t, _vp],
+                       ctypes.c_int),
     "mpdata_last_error": ([], ctypes.c_char_p),
     "mpdata_timing_enable": ([ctypes.c_int32], ctypes.c_int),
     "mpdata_timing_read": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
@@ -180,3 +182,63 @@ def timing_read(kind: int):
     n = ctypes.c_int64(0)
     _check(lib().mpdata_timing_read(kind, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def adjoint(psi0, cx, cy, cz, g, seed, nsteps, *, checkpoint_every=0, iters=2, limiter=True,
+            bc=("periodic", "closed", "closed"), eps=0.0, want_dcz=True):
+    """Reverse sweep of `run`: returns (dJ/dpsi0, dJ/dcx, dJ/dcy, dJ/dcz or None, psi_T)
+    for the seed dJ/dpsi_T (FP64)."""
+    import torch
+
+    stream = _fields(psi0, (cx, cy, cz, g, seed))
+    p = problem_for(tuple(psi0.shape), bc, iters, limiter, _dtype_code(psi0), eps)
+    nb = lib().mpdata_workspace_bytes(ctypes.byref(p), MPDATA_OP_ADJOINT, int(nsteps), int(checkpoint_every))
+    if nb == 0:
+        _check(MPDATA_EINVAL)
+    ws = _workspace(nb, psi0.device)
+    dpsi0 = torch.empty_like(psi0)
+    dcx, dcy = torch.empty_like(psi0), torch.empty_like(psi0)
+    dcz = torch.empty_like(psi0) if want_dcz else None
+    psiT = torch.empty_like(psi0)
+    _check(lib().mpdata_adjoint(ctypes.byref(p), int(nsteps), int(checkpoint_every), _ptr(psi0), _ptr(cx),
+                                _ptr(cy), _ptr(cz), _ptr(g), _ptr(seed), _ptr(dpsi0), _ptr(dcx), _ptr(dcy),
+                                _ptr(dcz), _ptr(psiT), _ptr(ws), ws.numel(), ctypes.c_void_p(stream)))
+    return dpsi0, dcx, dcy, dcz, psiT
+
+
+def _make_function():
+    import torch
+
+    class MPDATAFunction(torch.autograd.Function):
+        """(psi0, cx, cy, cz) -> psi_T after `nsteps` MPDATA steps; the backward
+        runs the library's hand-written adjoint (mpdata_adjoint) with
+        checkpoints every `checkpoint_every` steps.  g is a fixed metric."""
+
+        @staticmethod
+        def forward(ctx, psi0, cx, cy, cz, g, nsteps, checkpoint_every=0, iters=2, limiter=True,
+                    bc=("periodic", "closed", "closed")):
+            ctx.save_for_backward(psi0, cx, cy, cz, g)
+            ctx.cfg = (int(nsteps), int(checkpoint_every), int(iters), bool(limiter), tuple(bc))
+            out = psi0.detach().clone()
+            run(out, cx.detach(), cy.detach(), cz.detach(), g.detach(), nsteps, iters=iters, limiter=limiter, bc=bc)
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            psi0, cx, cy, cz, g = ctx.saved_tensors
+            nsteps, k, iters, limiter, bc = ctx.cfg
+            d0, dx, dy, dz, _ = adjoint(psi0.detach(), cx.detach(), cy.detach(), cz.detach(), g.detach(),
+                                        grad_out.contiguous(), nsteps, checkpoint_every=k, iters=iters,
+                                        limiter=limiter, bc=bc)
+            return d0, dx, dy, dz, None, None, None, None, None, None
+
+    return MPDATAFunction
+
+
+_fn_cache = []
+
+
+def mpdata_function():
+    if not _fn_cache:
+        _fn_cache.append(_make_function())
+    return _fn_cache[0]

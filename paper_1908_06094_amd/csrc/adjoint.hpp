@@ -1,0 +1,523 @@
+// adjoint.hpp -- reverse-mode (adjoint) kernels of one MPDATA step, FP64.
+//
+// Every kernel is a gather: one thread owns one cell and writes only that
+// cell's adjoint values (and those of its three "own" faces i+1/2, j+1/2,
+// k+1/2), collecting lambda(output) * d(output)/d(input) from every forward
+// output that read the input.  No atomics, so the adjoint is bitwise
+// reproducible.  The stage formulas are those of stages.hpp (the donor-cell
+// update of the paper's Listing 8 stages, the antidiffusive velocity, the
+// limiter bounds, beta and the limited velocities).  At kinks the derivative
+// follows the branch taken: [c]+ has derivative [c > 0], [c]- has [c < 0],
+// |c| has sign(c) with sign(0) = 0; min(1, min(a, b)) routes to the first
+// minimal entry of (1, a, b); the bounds route to the first extremal entry of
+// psi^n at (self, -x, +x, -y, +y, -z, +z), then phi in the same order.
+//
+// The antidiffusive velocity reads ~20 inputs per face, so its adjoint runs
+// in two kernels: the first evaluates each face's partial derivatives times
+// the face's adjoint once (nine values per face), the second gathers them.
+#pragma once
+
+#include "common.hpp"
+#include "stages.hpp"
+
+namespace mpdata {
+namespace adj {
+
+#pragma clang fp contract(off)
+
+using stages::at;
+using stages::Cell;
+using stages::cell_of_thread;
+using stages::closed;
+using stages::extent;
+
+// Linear index of the face c[axis]+1/2 for coordinates within one cell of the
+// domain (the coordinate along the axis in [-1, n-1]), or -1 at a closed wall.
+__device__ __forceinline__ long long face_idx(const Geo& g, int axis, int i, int j, int k)
+{
+    int c[3] = {i, j, k};
+    const int n = extent(g, axis);
+    for (int b = 0; b < 3; ++b)
+        if (b != axis) c[b] = nbr(c[b], extent(g, b), closed(g, b));
+    int f = c[axis];
+    if (closed(g, axis)) {
+        if (f < 0 || f >= n - 1) return -1;
+    } else if (f < 0) {
+        f += n;
+    }
+    c[axis] = f;
+    return (long long)c[2] * g.sz + (long long)c[1] * g.sy + c[0];
+}
+
+__device__ __forceinline__ double stp(double c) { return c > 0.0 ? 1.0 : 0.0; }    // d[c]+/dc
+__device__ __forceinline__ double stn(double c) { return c < 0.0 ? 1.0 : 0.0; }    // d[c]-/dc
+__device__ __forceinline__ double sgn(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? -1.0 : 0.0); }
+__device__ __forceinline__ double ppos(double c) { return c > 0.0 ? c : 0.0; }
+__device__ __forceinline__ double pneg(double c) { return c < 0.0 ? c : 0.0; }
+
+// Index (0, 1, 2) of the first minimal entry of (1, x, y).
+__device__ __forceinline__ int first_min3(double x, double y)
+{
+    const double m = min2(1.0, min2(x, y));
+    if (1.0 == m) return 0;
+    if (x == m) return 1;
+    return 2;
+}
+
+// ---------------------------------------------------------------------------
+// Donor-cell pass out = phi - div(F)/G:  lout -> lphi (+=), lvel (+=)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restrict__ phi, const double* __restrict__ u,
+                                                   const double* __restrict__ v, const double* __restrict__ w,
+                                                   const double* __restrict__ gm, const double* __restrict__ lout,
+                                                   double* __restrict__ lphi, double* __restrict__ lu,
+                                                   double* __restrict__ lv, double* __restrict__ lw)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double* vel[3] = {u, v, w};
+    double* lvel[3] = {lu, lv, lw};
+    double acc = lout[c.q];
+    const double mu_c = lout[c.q] / gm[c.q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // own face c+1/2: the flux leaves c and enters r
+        long long fo = face_idx(g, a, c.i, c.j, c.k);
+        if (fo >= 0 && vel[a] != nullptr) {
+            int r[3] = {c.i, c.j, c.k};
+            r[a] += 1;
+            const long long qr = at(g, r[0], r[1], r[2]);
+            const double lamf = lout[qr] / gm[qr] - mu_c;
+            const double vv = vel[a][fo];
+            acc += ppos(vv) * lamf;
+            if (lvel[a]) lvel[a][fo] += (stp(vv) * phi[c.q] + stn(vv) * phi[qr]) * lamf;
+        }
+        // left face c-1/2: c is the right cell of the flux
+        int l[3] = {c.i, c.j, c.k};
+        l[a] -= 1;
+        long long fl = face_idx(g, a, l[0], l[1], l[2]);
+        if (fl >= 0 && vel[a] != nullptr) {
+            const long long ql = at(g, l[0], l[1], l[2]);
+            const double lamf = mu_c - lout[ql] / gm[ql];
+            acc += pneg(vel[a][fl]) * lamf;
+        }
+    }
+    lphi[c.q] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// Limited velocities:  lvl -> lut (=), lbup (=), lbdn (=)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_limit(Geo g, const double* __restrict__ ut, const double* __restrict__ vt,
+                                                   const double* __restrict__ wt, const double* __restrict__ bup,
+                                                   const double* __restrict__ bdn, const double* __restrict__ lvx,
+                                                   const double* __restrict__ lvy, const double* __restrict__ lvz,
+                                                   double* __restrict__ lux, double* __restrict__ luy,
+                                                   double* __restrict__ luz, double* __restrict__ lbup,
+                                                   double* __restrict__ lbdn)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double* U3[3] = {ut, vt, wt};
+    const double* L3[3] = {lvx, lvy, lvz};
+    double* O3[3] = {lux, luy, luz};
+    double gup = 0.0, gdn = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // own face: c is its left cell
+        const long long fo = face_idx(g, a, c.i, c.j, c.k);
+        if (fo >= 0) {
+            int r[3] = {c.i, c.j, c.k};
+            r[a] += 1;
+            const long long qr = at(g, r[0], r[1], r[2]);
+            const double U = U3[a][fo], lam = L3[a][fo];
+            const double up = min2(1.0, min2(bdn[c.q], bup[qr]));
+            const double dn = min2(1.0, min2(bup[c.q], bdn[qr]));
+            O3[a][fo] = lam * (stp(U) * up + stn(U) * dn);
+            if (U > 0.0 && first_min3(bdn[c.q], bup[qr]) == 1) gdn += lam * U;
+            if (U < 0.0 && first_min3(bup[c.q], bdn[qr]) == 1) gup += lam * U;
+        } else {
+            // a wall's slot carries no velocity; give it a defined adjoint
+            if (closed(g, a)) O3[a][c.q] = 0.0;
+        }
+        // left face: c is its right cell
+        int l[3] = {c.i, c.j, c.k};
+        l[a] -= 1;
+        const long long fl = face_idx(g, a, l[0], l[1], l[2]);
+        if (fl >= 0) {
+            const long long ql = at(g, l[0], l[1], l[2]);
+            const double U = U3[a][fl], lam = L3[a][fl];
+            if (U > 0.0 && first_min3(bdn[ql], bup[c.q]) == 2) gup += lam * U;
+            if (U < 0.0 && first_min3(bup[ql], bdn[c.q]) == 2) gdn += lam * U;
+        }
+    }
+    lbup[c.q] = gup;
+    lbdn[c.q] = gdn;
+}
+
+// ---------------------------------------------------------------------------
+// Bounds (max / min over the 7-point cross of psi^n and phi)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cross7(const Geo& g, int i, int j, int k, long long idx[7])
+{
+    idx[0] = at(g, i, j, k);
+    idx[1] = at(g, i - 1, j, k);
+    idx[2] = at(g, i + 1, j, k);
+    idx[3] = at(g, i, j - 1, k);
+    idx[4] = at(g, i, j + 1, k);
+    idx[5] = at(g, i, j, k - 1);
+    idx[6] = at(g, i, j, k + 1);
+}
+
+__global__ void __launch_bounds__(256) k_bounds(Geo g, const double* __restrict__ psin, const double* __restrict__ phi,
+                                                double* __restrict__ mx, double* __restrict__ mn)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    long long idx[7];
+    cross7(g, c.i, c.j, c.k, idx);
+    double hi = psin[idx[0]], lo = hi;
+    for (int f = 0; f < 2; ++f)
+        for (int o = 0; o < 7; ++o) {
+            const double v = (f ? phi : psin)[idx[o]];
+            hi = max2(hi, v);
+            lo = min2(lo, v);
+        }
+    mx[c.q] = hi;
+    mn[c.q] = lo;
+}
+
+// (lmx, lmn) -> lpsin (+=), lphi (+=): each cell x collects from the distinct
+// cells whose cross contains it, where x is the first maximal / minimal entry.
+__global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const double* __restrict__ psin,
+                                                    const double* __restrict__ phi, const double* __restrict__ lmx,
+                                                    const double* __restrict__ lmn, double* __restrict__ lpsin,
+                                                    double* __restrict__ lphi)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    long long cand[7];
+    cross7(g, c.i, c.j, c.k, cand);   // the cells whose cross contains c (the cross is symmetric)
+    double gp = 0.0, gf = 0.0;
+    for (int m = 0; m < 7; ++m) {
+        bool dup = false;
+        for (int m2 = 0; m2 < m; ++m2) dup = dup || cand[m2] == cand[m];
+        if (dup) continue;
+        const long long qc = cand[m];
+        const int kk = (int)(qc / g.sz), jj = (int)((qc % g.sz) / g.sy), ii = (int)(qc % g.sy);
+        long long idx[7];
+        cross7(g, ii, jj, kk, idx);
+        int am = 0, an = 0;
+        double vm = psin[idx[0]], vn = vm;
+        for (int e = 1; e < 14; ++e) {
+            const double val = (e < 7 ? psin : phi)[idx[e % 7]];
+            if (val > vm) { vm = val; am = e; }
+            if (val < vn) { vn = val; an = e; }
+        }
+        if (idx[am % 7] == c.q) (am < 7 ? gp : gf) += lmx[qc];
+        if (idx[an % 7] == c.q) (an < 7 ? gp : gf) += lmn[qc];
+    }
+    lpsin[c.q] += gp;
+    lphi[c.q] += gf;
+}
+
+// ---------------------------------------------------------------------------
+// Limiter coefficients beta_up = (mx - phi) G / (in + eps),
+// beta_dn = (phi - mn) G / (out + eps).
+// Kernel 1 (per cell): the adjoints of in and out (lin, lout), of mx and mn,
+// and beta's direct dependence on phi.  Kernel 2 (gather): in and out's
+// dependence on phi and on the antidiffusive velocities.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void in_out(const Geo& g, const Cell& c, const double* __restrict__ phi,
+                                       const double* const U3[3], double& in, double& out)
+{
+    double fin[3], fout[3];
+    const double pc = phi[c.q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int l[3] = {c.i, c.j, c.k}, r[3] = {c.i, c.j, c.k};
+        l[a] -= 1;
+        r[a] += 1;
+        const long long fr = face_idx(g, a, c.i, c.j, c.k);
+        const long long fl = face_idx(g, a, l[0], l[1], l[2]);
+        const double vr = fr < 0 ? 0.0 : U3[a][fr];
+        const double vl = fl < 0 ? 0.0 : U3[a][fl];
+        fin[a] = ppos(vl) * phi[at(g, l[0], l[1], l[2])] - pneg(vr) * phi[at(g, r[0], r[1], r[2])];
+        fout[a] = ppos(vr) * pc - pneg(vl) * pc;
+    }
+    in = (fin[0] + fin[1]) + fin[2];
+    out = (fout[0] + fout[1]) + fout[2];
+}
+
+__global__ void __launch_bounds__(256) k_adj_beta1(Geo g, double eps, const double* __restrict__ phi,
+                                                   const double* __restrict__ ut, const double* __restrict__ vt,
+                                                   const double* __restrict__ wt, const double* __restrict__ mx,
+                                                   const double* __restrict__ mn, const double* __restrict__ gm,
+                                                   const double* __restrict__ lbup, const double* __restrict__ lbdn,
+                                                   double* __restrict__ lin, double* __restrict__ lout,
+                                                   double* __restrict__ lmx, double* __restrict__ lmn,
+                                                   double* __restrict__ lphi)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double* U3[3] = {ut, vt, wt};
+    double in, out;
+    in_out(g, c, phi, U3, in, out);
+    const double din = in + eps, dout = out + eps;
+    const double G = gm[c.q], pc = phi[c.q];
+    const double bu = ((mx[c.q] - pc) * G) / din;
+    const double bd = ((pc - mn[c.q]) * G) / dout;
+    const double gu = lbup[c.q], gd = lbdn[c.q];
+    lmx[c.q] = gu * G / din;
+    lmn[c.q] = -(gd * G / dout);
+    lphi[c.q] += -gu * G / din + gd * G / dout;
+    lin[c.q] = -gu * bu / din;
+    lout[c.q] = -gd * bd / dout;
+}
+
+// in(c)  = sum_a [U(c-1/2)]+ phi(c-1) - [U(c+1/2)]- phi(c+1)
+// out(c) = sum_a ([U(c+1/2)]+ - [U(c-1/2)]-) phi(c)
+__global__ void __launch_bounds__(256) k_adj_beta2(Geo g, const double* __restrict__ phi, const double* __restrict__ ut,
+                                                   const double* __restrict__ vt, const double* __restrict__ wt,
+                                                   const double* __restrict__ lin, const double* __restrict__ lout,
+                                                   double* __restrict__ lphi, double* __restrict__ lux,
+                                                   double* __restrict__ luy, double* __restrict__ luz)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double* U3[3] = {ut, vt, wt};
+    double* L3[3] = {lux, luy, luz};
+    const double pc = phi[c.q];
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int l[3] = {c.i, c.j, c.k}, r[3] = {c.i, c.j, c.k};
+        l[a] -= 1;
+        r[a] += 1;
+        const long long fo = face_idx(g, a, c.i, c.j, c.k);
+        const long long fl = face_idx(g, a, l[0], l[1], l[2]);
+        if (fo >= 0) {
+            const long long qr = at(g, r[0], r[1], r[2]);
+            const double U = U3[a][fo];
+            // c is the left cell of its own face: inflow term of r, outflow term of c
+            acc += lin[qr] * ppos(U) + lout[c.q] * ppos(U);
+            // the face's own adjoint: in(r), in(c), out(c), out(r)
+            L3[a][fo] += lin[qr] * stp(U) * pc - lin[c.q] * stn(U) * phi[qr] + lout[c.q] * stp(U) * pc -
+                         lout[qr] * stn(U) * phi[qr];
+        }
+        if (fl >= 0) {
+            const long long ql = at(g, l[0], l[1], l[2]);
+            const double U = U3[a][fl];
+            // c is the right cell of its left face: inflow term of l, outflow term of c
+            acc += -lin[ql] * pneg(U) - lout[c.q] * pneg(U);
+        }
+    }
+    lphi[c.q] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// Antidiffusive velocity
+//   U~ = (|U| - U^2/Gf) A - (U/Gf) (Vb_1 B_1 + Vb_2 B_2)
+//   A = (pR - pL)/(pR + pL + eps), B_t = (Sp - Sm)/(2 (Sp + Sm + eps)),
+//   Sp = phi(R+t) + phi(L+t), Sm = phi(R-t) + phi(L-t),
+//   Vb_t = (V_t(L) + V_t(R) + V_t(L-t) + V_t(R-t))/4, Gf = (G(L) + G(R))/2.
+// Kernel 1 stores, per face (axis a, left cell y), lambda times:
+//   s0 dU~/dpR, s1 dU~/dpL, s2/s3 dU~/dSp_1, dU~/dSm_1, s4/s5 the same for
+//   the second transverse axis, s6/s7 dU~/dV_t of each of the four faces
+//   of transverse axis t, s8 dU~/dU.
+// ---------------------------------------------------------------------------
+constexpr int kSlots = 9;
+
+__global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const double* __restrict__ phi,
+                                                       const double* __restrict__ u, const double* __restrict__ v,
+                                                       const double* __restrict__ w, const double* __restrict__ gm,
+                                                       const double* __restrict__ lux, const double* __restrict__ luy,
+                                                       const double* __restrict__ luz, double* __restrict__ slots,
+                                                       long long field)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double* vel[3] = {u, v, w};
+    const double* lam3[3] = {lux, luy, luz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double* s = slots + (long long)a * kSlots * field + c.q;
+        const long long fo = face_idx(g, a, c.i, c.j, c.k);
+        if (fo < 0) {
+            for (int e = 0; e < kSlots; ++e) s[e * field] = 0.0;
+            continue;
+        }
+        int R[3] = {c.i, c.j, c.k};
+        R[a] += 1;
+        const double lam = lam3[a][c.q];
+        const double pL = phi[c.q], pR = phi[at(g, R[0], R[1], R[2])];
+        const double D0 = (pR + pL) + eps;
+        const double A = (pR - pL) / D0;
+        double B[2], Vb[2], Dt[2], Sp[2], Sm[2];
+        int sidx = 0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t == a) continue;
+            int Lp[3] = {c.i, c.j, c.k}, Rp[3] = {R[0], R[1], R[2]};
+            int Lm[3] = {c.i, c.j, c.k}, Rm[3] = {R[0], R[1], R[2]};
+            Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
+            Sp[sidx] = phi[at(g, Rp[0], Rp[1], Rp[2])] + phi[at(g, Lp[0], Lp[1], Lp[2])];
+            Sm[sidx] = phi[at(g, Rm[0], Rm[1], Rm[2])] + phi[at(g, Lm[0], Lm[1], Lm[2])];
+            Dt[sidx] = (Sp[sidx] + Sm[sidx]) + eps;
+            B[sidx] = 0.5 * ((Sp[sidx] - Sm[sidx]) / Dt[sidx]);
+            const long long f0 = face_idx(g, t, c.i, c.j, c.k), f1 = face_idx(g, t, R[0], R[1], R[2]);
+            const long long f2 = face_idx(g, t, Lm[0], Lm[1], Lm[2]), f3 = face_idx(g, t, Rm[0], Rm[1], Rm[2]);
+            const double* vt = vel[t];
+            const double v0 = (f0 < 0 || !vt) ? 0.0 : vt[f0], v1 = (f1 < 0 || !vt) ? 0.0 : vt[f1];
+            const double v2 = (f2 < 0 || !vt) ? 0.0 : vt[f2], v3 = (f3 < 0 || !vt) ? 0.0 : vt[f3];
+            Vb[sidx] = 0.25 * ((v0 + v1) + (v2 + v3));
+            ++sidx;
+        }
+        const double Gf = 0.5 * (gm[c.q] + gm[at(g, R[0], R[1], R[2])]);
+        const double U = vel[a] ? vel[a][fo] : 0.0;
+        const double S = (Vb[0] * B[0]) + (Vb[1] * B[1]);
+        const double dU = (sgn(U) - 2.0 * U / Gf) * A - S / Gf;
+        const double dA = (U < 0.0 ? -U : U) - (U * U) / Gf;
+        const double dS = -U / Gf;
+        const double gA = lam * dA;
+        s[0 * field] = gA * (2.0 * pL + eps) / (D0 * D0);
+        s[1 * field] = -(gA * (2.0 * pR + eps) / (D0 * D0));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double gB = lam * dS * Vb[q];
+            s[(2 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) / (Dt[q] * Dt[q]));
+            s[(3 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) / (Dt[q] * Dt[q]));
+            s[(6 + q) * field] = 0.25 * (lam * dS * B[q]);
+        }
+        s[8 * field] = lam * dU;
+    }
+}
+
+// Kernel 2: each cell x gathers the slots of the faces that read phi(x), and
+// of the faces that read the velocities of its three own faces.  Candidate
+// faces come from the stencil offsets; every candidate's actual inputs are
+// recomputed through the halo rules and compared with x, so wrap, clamp and
+// tiny grids (where one cell fills several input positions) are exact.
+__global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
+                                                       double* __restrict__ lphi, double* __restrict__ lu,
+                                                       double* __restrict__ lv, double* __restrict__ lw)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    double* lvel[3] = {lu, lv, lw};
+    const long long x = c.q;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) {
+        int tr[2];
+        {
+            int n = 0;
+            for (int t = 0; t < 3; ++t)
+                if (t != a) tr[n++] = t;
+        }
+        // input offsets of face (a, y): L, R, L+-t1, R+-t1, L+-t2, R+-t2
+        int off[10][3];
+        int slot_of[10];
+        {
+            int n = 0;
+            for (int e = 0; e < 2; ++e) {
+                off[n][0] = off[n][1] = off[n][2] = 0;
+                off[n][a] = e;
+                slot_of[n] = e == 1 ? 0 : 1;
+                ++n;
+            }
+            for (int q = 0; q < 2; ++q)
+                for (int sg = 1; sg >= -1; sg -= 2)
+                    for (int e = 0; e < 2; ++e) {
+                        off[n][0] = off[n][1] = off[n][2] = 0;
+                        off[n][a] = e;
+                        off[n][tr[q]] = sg;
+                        slot_of[n] = 2 + 2 * q + (sg > 0 ? 0 : 1);
+                        ++n;
+                    }
+        }
+        long long seen[10];
+        int nseen = 0;
+        for (int m = 0; m < 10; ++m) {
+            const long long y = at(g, c.i - off[m][0], c.j - off[m][1], c.k - off[m][2]);
+            bool dup = false;
+            for (int s2 = 0; s2 < nseen; ++s2) dup = dup || seen[s2] == y;
+            if (dup) continue;
+            seen[nseen++] = y;
+            const int yk = (int)(y / g.sz), yj = (int)((y % g.sz) / g.sy), yi = (int)(y % g.sy);
+            if (face_idx(g, a, yi, yj, yk) < 0) continue;   // wall: U~ is the constant 0
+            const double* s = slots + (long long)a * kSlots * field + y;
+            for (int e = 0; e < 10; ++e) {
+                if (at(g, yi + off[e][0], yj + off[e][1], yk + off[e][2]) == x) acc += s[slot_of[e] * field];
+            }
+        }
+    }
+    lphi[x] += acc;
+
+    // velocities of x's own faces: face (t, x) is read as the own velocity of
+    // face (t, x) and in the transverse averages of faces (a != t, y) at
+    // V_t(y), V_t(y+a), V_t(y-t), V_t(y+a-t)
+#pragma unroll 1
+    for (int t = 0; t < 3; ++t) {
+        if (!lvel[t]) continue;
+        const long long fx = face_idx(g, t, c.i, c.j, c.k);
+        if (fx < 0) continue;
+        double accv = slots[((long long)t * kSlots + 8) * field + x];
+        for (int a = 0; a < 3; ++a) {
+            if (a == t) continue;
+            // position of t among a's transverse axes in increasing order
+            const int q = (t == (a == 0 ? 1 : 0)) ? 0 : 1;
+            int o4[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            o4[1][a] = 1;
+            o4[2][t] = -1;
+            o4[3][a] = 1;
+            o4[3][t] = -1;
+            long long seen[4];
+            int nseen = 0;
+            for (int m = 0; m < 4; ++m) {
+                int yc[3] = {c.i - o4[m][0], c.j - o4[m][1], c.k - o4[m][2]};
+                // the face coordinate along t stays a face index: map the
+                // other axes only (wrap / clamp), then require a valid cell
+                int yt = yc[t];
+                const int nt = extent(g, t);
+                if (yt < 0) {
+                    if (closed(g, t)) continue;
+                    yt += nt;
+                } else if (yt >= nt) {
+                    if (closed(g, t)) continue;
+                    yt -= nt;
+                }
+                yc[t] = yt;
+                const long long y = at(g, yc[0], yc[1], yc[2]);
+                bool dup = false;
+                for (int s2 = 0; s2 < nseen; ++s2) dup = dup || seen[s2] == y;
+                if (dup) continue;
+                seen[nseen++] = y;
+                const int yk = (int)(y / g.sz), yj = (int)((y % g.sz) / g.sy), yi = (int)(y % g.sy);
+                if (face_idx(g, a, yi, yj, yk) < 0) continue;
+                int ry[3] = {yi, yj, yk};
+                ry[a] += 1;
+                int lm[3] = {yi, yj, yk};
+                lm[t] -= 1;
+                int rm[3] = {ry[0], ry[1], ry[2]};
+                rm[t] -= 1;
+                int hits = (face_idx(g, t, yi, yj, yk) == fx) + (face_idx(g, t, ry[0], ry[1], ry[2]) == fx) +
+                           (face_idx(g, t, lm[0], lm[1], lm[2]) == fx) + (face_idx(g, t, rm[0], rm[1], rm[2]) == fx);
+                if (hits) accv += hits * slots[((long long)a * kSlots + 6 + q) * field + y];
+            }
+        }
+        lvel[t][fx] += accv;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_axpy(long long n, double a, const double* __restrict__ x,
+                                              double* __restrict__ y)
+{
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) y[q] += a * x[q];
+}
+
+#pragma clang fp contract(on)
+
+}  // namespace adj
+}  // namespace mpdata

@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "stages.hpp"
 #include "fused.hpp"
+#include "adjoint.hpp"
 
 namespace {
 
@@ -417,6 +418,191 @@ __global__ void __launch_bounds__(kMassThreads) k_mass_final(int nparts, double*
     if (threadIdx.x == 0) part[2 * nparts] = ss[0] + sc[0];
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint driver (FP64)
+// ---------------------------------------------------------------------------
+
+struct AdjLayout {
+    long long n;          // cells
+    size_t fb;            // bytes per field
+    int segs, K;          // checkpoints, steps per segment
+    int M;                // passes per step
+    size_t fields;        // total fields
+};
+
+AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
+{
+    AdjLayout L;
+    L.n = cells(p);
+    L.fb = ((size_t)L.n * sizeof(double) + 255) & ~(size_t)255;
+    L.K = K;
+    L.segs = nsteps > 0 ? (nsteps + K - 1) / K : 1;
+    L.M = p->iters;
+    // checkpoints + segment states + per pass (phi, U~ x3, V x3, beta x2, mx,
+    // mn) + 18 adjoint fields (cur, prev, psin, V x3, Vprev x3, U~ x3, beta x2,
+    // lin, lout, lmx, lmn) + antidiffusive slots (27) + a forward step's
+    // workspace + a zero field and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)11 * L.M + 18 + 27 + kStepFields + 2;
+    return L;
+}
+
+int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, const double* cx, const double* cy,
+                const double* cz, const double* gm, const double* seed, double* dpsi0, double* dcx, double* dcy,
+                double* dcz, double* psiT, void* ws, hipStream_t st)
+{
+    namespace A = mpdata::adj;
+    namespace S = mpdata::stages;
+    const AdjLayout L = adj_layout(p, nsteps, K);
+    const long long n = L.n;
+    char* base = (char*)ws;
+    size_t next = 0;
+    auto field = [&]() { double* f = (double*)(base + L.fb * next); ++next; return f; };
+    std::vector<double*> ckpt(L.segs), seg(K);
+    for (auto& f : ckpt) f = field();
+    for (auto& f : seg) f = field();
+    const int M = L.M;
+    std::vector<double*> phis(M + 1, nullptr), ut(3 * (M + 1), nullptr), vl(3 * (M + 1), nullptr),
+        bu(M + 1, nullptr), bd(M + 1, nullptr), mx(M + 1, nullptr), mn(M + 1, nullptr);
+    for (int m = 1; m <= M; ++m) {
+        phis[m] = field();
+        bu[m] = field();
+        bd[m] = field();
+        mx[m] = field();
+        mn[m] = field();
+        for (int a = 0; a < 3; ++a) {
+            ut[3 * m + a] = field();
+            vl[3 * m + a] = field();
+        }
+    }
+    double* lcur = field();
+    double* lprev = field();
+    double* lpsin = field();
+    double* lv[3] = {field(), field(), field()};
+    double* lvp[3] = {field(), field(), field()};
+    double* lut[3] = {field(), field(), field()};
+    double* lbu = field();
+    double* lbd = field();
+    double* lin = field();
+    double* lout = field();
+    double* lmx = field();
+    double* lmn = field();
+    double* slots = field();
+    next += 26;                       // the 27 slot fields are contiguous
+    void* step_ws = base + L.fb * next;
+    next += kStepFields;
+    double* zero_w = field();
+    double* dcz_scratch = field();
+    const long long slot_stride = (long long)(L.fb / sizeof(double));
+    if (next != L.fields)   // the carve above must match the size the caller allocated
+        return fail(MPDATA_EINVAL, "internal: adjoint workspace layout mismatch (%zu != %zu fields)", next,
+                    L.fields);
+
+    mpdata::Geo g = geo_of(p);
+    dim3 blk(64, 4, 1);
+    dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
+    const double eps = p->eps > 0.0 ? p->eps : 1e-15;
+    auto fill0 = [&](double* a) { mpdata::k_fill<double><<<1024, 256, 0, st>>>(a, n, 0.0); };
+    hipError_t copy_err = hipSuccess;
+    auto copy = [&](double* dst, const double* src) {
+        hipError_t e = hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (copy_err == hipSuccess) copy_err = e;
+    };
+    if (!cz) {
+        fill0(zero_w);
+        cz = zero_w;
+    }
+    double* dcz_t = dcz ? dcz : dcz_scratch;   // without a dcz output its sums land in scratch
+    const double* C3[3] = {cx, cy, cz};
+    double* dC[3] = {dcx, dcy, dcz_t};
+    Timed tm(MPDATA_KERNEL_STAGE, st);
+
+    // forward sweep: psi^{cK} into checkpoint c, other states ping-pong
+    // between two scratch fields (the adjoint ones, unused until the reverse)
+    copy(ckpt[0], psi0);
+    const double* cur = ckpt[0];
+    double* pp[2] = {lprev, lpsin};
+    for (int s = 0; s < nsteps; ++s) {
+        const bool store = (s + 1) % K == 0 && (s + 1) / K < L.segs;
+        double* dst = store ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
+        if (int rc = dispatch_step(p, cur, dst, cx, cy, cz, gm, step_ws, st)) return rc;
+        cur = dst;
+    }
+    if (psiT && cur != psiT) copy(psiT, cur);
+
+    copy(lcur, seed);
+    for (int a = 0; a < 3; ++a) fill0(dC[a]);
+
+    for (int sg = L.segs - 1; sg >= 0; --sg) {
+        const int s0 = sg * K;
+        const int s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
+        // states psi^{s0} .. psi^{s1-1} of the segment
+        copy(seg[0], ckpt[sg]);
+        for (int s = s0 + 1; s < s1; ++s)
+            if (int rc = dispatch_step(p, seg[s - 1 - s0], seg[s - s0], cx, cy, cz, gm, step_ws, st)) return rc;
+        for (int s = s1 - 1; s >= s0; --s) {
+            const double* psin = seg[s - s0];
+            // the step's intermediates, stage by stage
+            S::k_donor<double><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, phis[1]);
+            for (int m = 2; m <= M; ++m) {
+                const double* prev[3];
+                for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : vl[3 * (m - 1) + a];
+                double* U3[3] = {ut[3 * m], ut[3 * m + 1], ut[3 * m + 2]};
+                double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
+                S::k_antidiff<double><<<grd, blk, 0, st>>>(g, eps, phis[m - 1], prev[0], prev[1], prev[2], gm, U3[0],
+                                                          U3[1], U3[2]);
+                for (int a = 0; a < 3; ++a) copy(V3[a], U3[a]);
+                if (p->limiter) {
+                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, phis[m - 1], mx[m], mn[m]);
+                    S::k_beta<double><<<grd, blk, 0, st>>>(g, eps, psin, phis[m - 1], U3[0], U3[1], U3[2], gm, bu[m],
+                                                          bd[m]);
+                    S::k_limit<double><<<grd, blk, 0, st>>>(g, V3[0], V3[1], V3[2], bu[m], bd[m]);
+                }
+                S::k_donor<double><<<grd, blk, 0, st>>>(g, phis[m - 1], V3[0], V3[1], V3[2], gm, phis[m]);
+            }
+            if (int rc = launch_status("adjoint recompute")) return rc;
+
+            // reverse through the passes
+            fill0(lpsin);
+            for (int a = 0; a < 3; ++a) fill0(lv[a]);
+            for (int m = M; m >= 2; --m) {
+                const double* ph = phis[m - 1];
+                const double* prev[3];
+                for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : vl[3 * (m - 1) + a];
+                const double* U3[3] = {ut[3 * m], ut[3 * m + 1], ut[3 * m + 2]};
+                const double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
+                fill0(lprev);
+                if (m > 2)
+                    for (int a = 0; a < 3; ++a) fill0(lvp[a]);
+                A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1], lv[2]);
+                if (p->limiter) {
+                    A::k_adj_limit<<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], bu[m], bd[m], lv[0], lv[1], lv[2],
+                                                        lut[0], lut[1], lut[2], lbu, lbd);
+                    A::k_adj_beta1<<<grd, blk, 0, st>>>(g, eps, ph, U3[0], U3[1], U3[2], mx[m], mn[m], gm, lbu, lbd,
+                                                        lin, lout, lmx, lmn, lprev);
+                    A::k_adj_beta2<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, lprev, lut[0], lut[1],
+                                                        lut[2]);
+                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, psin, ph, lmx, lmn, lpsin, lprev);
+                } else {
+                    for (int a = 0; a < 3; ++a) copy(lut[a], lv[a]);
+                }
+                double* tgt[3];
+                for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
+                A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lut[0], lut[1],
+                                                        lut[2], slots, slot_stride);
+                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
+                std::swap(lcur, lprev);
+                for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
+            }
+            A::k_adj_donor<<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, lcur, lpsin, dC[0], dC[1], dC[2]);
+            std::swap(lcur, lpsin);
+            if (int rc = launch_status("adjoint step")) return rc;
+        }
+    }
+    copy(dpsi0, lcur);
+    if (copy_err != hipSuccess) return fail(MPDATA_EDEVICE, "adjoint copies: %s", hipGetErrorString(copy_err));
+    return ok();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -463,13 +649,17 @@ int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches)
 
 size_t mpdata_workspace_bytes(const mpdata_problem* p, int32_t op, int32_t nsteps, int32_t checkpoint_every)
 {
-    (void)nsteps;
-    (void)checkpoint_every;
     if (validate(p) != MPDATA_OK) return 0;
     switch (op) {
     case MPDATA_OP_STEP: return step_bytes(p);
     case MPDATA_OP_RUN: return step_bytes(p) + field_bytes(p);
     case MPDATA_OP_MASS: return kMassBytes;
+    case MPDATA_OP_ADJOINT: {
+        if (nsteps < 0) { fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps); return 0; }
+        int K = checkpoint_every > 0 ? checkpoint_every : (nsteps > 0 ? nsteps : 1);
+        AdjLayout L = adj_layout(p, nsteps, K);
+        return L.fields * L.fb;
+    }
     default: fail(MPDATA_EUNSUPPORTED, "workspace query for op=%d is not supported", op); return 0;
     }
 }
@@ -521,6 +711,35 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* c
         if (e != hipSuccess) return fail(MPDATA_EDEVICE, "final copy: %s", hipGetErrorString(e));
     }
     return ok();
+}
+
+int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_every, const void* psi0,
+                   const void* cx, const void* cy, const void* cz, const void* g, const void* dJ_dpsiT,
+                   void* dJ_dpsi0, void* dJ_dcx, void* dJ_dcy, void* dJ_dcz, void* psiT_out, void* ws,
+                   size_t ws_bytes, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (p->dtype != MPDATA_F64) return fail(MPDATA_EUNSUPPORTED, "the adjoint is implemented in FP64 only");
+    if (nsteps < 0) return fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps);
+    if (checkpoint_every < 0) return fail(MPDATA_EINVAL, "checkpoint_every=%d is negative", checkpoint_every);
+    const void* req[] = {psi0, cx, cy, g, dJ_dpsiT, dJ_dpsi0, dJ_dcx, dJ_dcy};
+    const char* names[] = {"psi0", "cx", "cy", "g", "dJ_dpsiT", "dJ_dpsi0", "dJ_dcx", "dJ_dcy"};
+    for (int e = 0; e < 8; ++e)
+        if (int rc = check_ptr(req[e], names[e], p)) return rc;
+    if (cz && !aligned(cz, 8)) return fail(MPDATA_EINVAL, "cz is not aligned to its element size");
+    if (dJ_dcz && !aligned(dJ_dcz, 8)) return fail(MPDATA_EINVAL, "dJ_dcz is not aligned to its element size");
+    if (psiT_out && !aligned(psiT_out, 8)) return fail(MPDATA_EINVAL, "psiT_out is not aligned");
+    if (dJ_dpsi0 == psi0 || dJ_dpsi0 == dJ_dpsiT)
+        return fail(MPDATA_EINVAL, "dJ_dpsi0 must not alias psi0 or dJ_dpsiT");
+    if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
+    const int K = checkpoint_every > 0 ? checkpoint_every : (nsteps > 0 ? nsteps : 1);
+    const AdjLayout L = adj_layout(p, nsteps, K);
+    if (ws_bytes < L.fields * L.fb)
+        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the adjoint needs", ws_bytes,
+                    L.fields * L.fb);
+    return adjoint_run(p, nsteps, K, (const double*)psi0, (const double*)cx, (const double*)cy, (const double*)cz,
+                       (const double*)g, (const double*)dJ_dpsiT, (double*)dJ_dpsi0, (double*)dJ_dcx,
+                       (double*)dJ_dcy, (double*)dJ_dcz, (double*)psiT_out, ws, (hipStream_t)stream);
 }
 
 int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g, double* host_out, void* ws,
