@@ -98,7 +98,7 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
  * recomputed from psi0: states are kept every checkpoint_every steps (0 =
  * only psi0) and each segment is recomputed before its reverse sweep.  At
  * the kinks of max/min the derivative follows the branch the forward step
- * took ([c]+ differentiates to [c > 0], |c| to sign(c) with sign(0) = 0,
+ * took ([c]+ differentiates to [c > 0], 1/2 at c = 0, |c| to sign(c) with sign(0) = 0,
  * min(1, min(a, b)) to its first minimal entry, the limiter bounds to their
  * first extremal entry).  psiT_out (nullable) receives psi_T.  No atomics:
  * the result is bitwise reproducible.  ws: at least the MPDATA_OP_ADJOINT

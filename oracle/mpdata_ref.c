@@ -469,8 +469,8 @@ int ref_num_threads(void)
 /* distributes lam(output) * d(output)/d(input) to the inputs it      */
 /* read, through the same halo rules the forward stage used.  At the  */
 /* kinks the derivative follows the branch taken:                     */
-/*   [c]+ has derivative [c > 0], [c]- has [c < 0], |c| has sign(c)   */
-/*   with sign(0) = 0;                                                */
+/*   [c]+ and [c]- have derivatives [c > 0] and [c < 0], and 1/2     */
+/*   each at c = 0; |c| has sign(c) with sign(0) = 0;                 */
 /*   min(1, min(a, b)) routes to the first minimal entry of (1, a, b) */
 /*   (nothing when it is the constant 1);                             */
 /*   the bounds route to the first extremal entry of the list         */
@@ -500,8 +500,12 @@ static int64_t face_lin(const ref_problem* p, int axis, const int c[3])
     return lin(p, d[0], d[1], d[2]);
 }
 
-static double step_fn(double c) { return c > 0.0 ? 1.0 : 0.0; }     /* d[c]+/dc */
-static double stepn_fn(double c) { return c < 0.0 ? 1.0 : 0.0; }    /* d[c]-/dc */
+/* d[c]+/dc and d[c]-/dc.  At c = 0 exactly both are 1/2, the symmetric
+ * subgradient: a donor flux [c]+ pL + [c]- pR then has slope (pL + pR)/2,
+ * its true derivative whenever pL == pR (which is common: an exactly uniform
+ * region gives exactly zero antidiffusive velocities). */
+static double step_fn(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? 0.0 : 0.5); }
+static double stepn_fn(double c) { return c < 0.0 ? 1.0 : (c > 0.0 ? 0.0 : 0.5); }
 static double sgn(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? -1.0 : 0.0); }
 
 /* Adjoint of ref_donor: lout -> lphi (+=), lvel[a] (+=). */

@@ -87,7 +87,8 @@ int ref_mass(const ref_problem* p, const double* psi, const double* g,
  * cost J(psi_T), returns dJ/dpsi0 and dJ/d(cx, cy, cz) (dcz may be NULL).
  * Every step's intermediates are recomputed from stored step states; at the
  * kinks of max/min the derivative follows the argument taken, the first
- * extremal one in a fixed order (see mpdata_ref.c).  Plain scatter loops,
+ * extremal one in a fixed order, and [c]+- take slope 1/2 at c = 0 (see
+ * mpdata_ref.c).  Plain scatter loops,
  * serial. */
 int ref_adjoint(const ref_problem* p, int32_t nsteps, const double* psi0,
                 const double* cx, const double* cy, const double* cz,

@@ -8,7 +8,7 @@
 // update of the paper's Listing 8 stages, the antidiffusive velocity, the
 // limiter bounds, beta and the limited velocities).  At kinks the derivative
 // follows the branch taken: [c]+ has derivative [c > 0], [c]- has [c < 0],
-// |c| has sign(c) with sign(0) = 0; min(1, min(a, b)) routes to the first
+// each 1/2 at c = 0; |c| has sign(c) with sign(0) = 0; min(1, min(a, b)) routes to the first
 // minimal entry of (1, a, b); the bounds route to the first extremal entry of
 // psi^n at (self, -x, +x, -y, +y, -z, +z), then phi in the same order.
 //
@@ -49,8 +49,10 @@ __device__ __forceinline__ long long face_idx(const Geo& g, int axis, int i, int
     return (long long)c[2] * g.sz + (long long)c[1] * g.sy + c[0];
 }
 
-__device__ __forceinline__ double stp(double c) { return c > 0.0 ? 1.0 : 0.0; }    // d[c]+/dc
-__device__ __forceinline__ double stn(double c) { return c < 0.0 ? 1.0 : 0.0; }    // d[c]-/dc
+// d[c]+/dc and d[c]-/dc, each 1/2 at c = 0 (the symmetric subgradient: exact
+// for a donor flux whose upwind and downwind values are equal)
+__device__ __forceinline__ double stp(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? 0.0 : 0.5); }
+__device__ __forceinline__ double stn(double c) { return c < 0.0 ? 1.0 : (c > 0.0 ? 0.0 : 0.5); }
 __device__ __forceinline__ double sgn(double c) { return c > 0.0 ? 1.0 : (c < 0.0 ? -1.0 : 0.0); }
 __device__ __forceinline__ double ppos(double c) { return c > 0.0 ? c : 0.0; }
 __device__ __forceinline__ double pneg(double c) { return c < 0.0 ? c : 0.0; }

@@ -75,3 +75,34 @@ def test_adjoint_zero_steps_is_identity():
     seed = np.arange(24.0).reshape(shape)
     d = oracle.adjoint(p, 0, psi, cx, cy, cz, g, seed)
     assert np.array_equal(d[0], seed) and not d[1].any() and not d[2].any() and not d[3].any()
+
+
+@pytest.mark.parametrize("iters", [2, 3])
+def test_adjoint_exact_on_uniform_background(iters):
+    """A cosine bell on an exactly uniform background (lat-lon metric,
+    solid-body winds, no limiter): over the uniform region the antidiffusive
+    velocities are exactly 0, where the donor flux [U]+ pL + [U]- pR is
+    differentiable with slope pL = pR.  The adjoint must take that slope
+    (the symmetric subgradient 1/2 of [c]+- at c = 0); central differences
+    are smooth here and pin it."""
+    nx, ny, nz = 32, 16, 3
+    cx, cy, cz, _ = workloads.stream_winds(nx, ny, nz, "solid", 0.5)
+    g = workloads.metric(nx, ny, nz)
+    psi = 0.5 + np.broadcast_to(workloads.cosine_bell(nx, ny)[None], (nz, ny, nx)).copy()
+    p = oracle.RefProblem(nx, ny, nz, bc=(P, C, C), iters=iters, limiter=False)
+    w = np.random.default_rng(5).uniform(0, 1, size=psi.shape)
+    steps = 5
+    out = oracle.run(p, steps, psi, cx, cy, cz, g)
+    grads = oracle.adjoint(p, steps, psi, cx, cy, cz, g, 2.0 * w * out)
+    rng = np.random.default_rng(1)
+    base = [psi, cx, cy, cz]
+    for which in range(3):
+        d = [np.zeros(psi.shape) for _ in range(4)]
+        d[which] = rng.standard_normal(psi.shape) * (1.0 if which == 0 else 0.1)
+        if which:
+            d[which][base[which] == 0.0] = 0.0
+        eps = 1e-6
+        fd = (_cost(p, steps, *[x + eps * y for x, y in zip(base, d)], g, w)
+              - _cost(p, steps, *[x - eps * y for x, y in zip(base, d)], g, w)) / (2 * eps)
+        ad = sum(float(np.sum(a * b)) for a, b in zip(grads, d))
+        assert abs(fd - ad) <= 1e-5 * abs(fd), (which, fd, ad)
