@@ -111,6 +111,43 @@ int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_e
                    void* dJ_dcy, void* dJ_dcz, void* psiT_out, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* Batched runs: many independent problems, each with ntracers tracer fields
+ * advected by the same winds and metric, all in one persistent launch per
+ * pass (the fused corrective pass over a work list of (problem, tile, tracer,
+ * plane) units, cut into equal ranges per workgroup).  The caller's problem
+ * struct supplies bc, iters, limiter, dtype and eps for every item (its sizes
+ * are ignored); each item supplies its sizes and device pointers.  psi holds
+ * the item's ntracers fields consecutively ([tracer][nz][ny][nx]); cz may be
+ * NULL.  Items must not share psi storage.  Flags:
+ *   MPDATA_BATCH_GRAPH  capture the nsteps steps into a HIP graph on first
+ *                       use and replay it (cached per item pointers, sizes,
+ *                       nsteps, workspace and device);
+ *   MPDATA_BATCH_TUNE   pick the kernel variant (one or two workgroups per
+ *                       CU) by timing one step of each on this batch; the
+ *                       choice is kept per batch shape and appended to the
+ *                       file named by the environment variable
+ *                       MPDATA_TUNE_CACHE.  Tuning synchronises `stream`.
+ * ws: at least mpdata_batch_workspace_bytes() for the same items.  The
+ * paper's fusion and caching of the flux stages (Section 6.1, Table 2,
+ * Listing 9) is what the fused pass applies; batching is this library's. */
+typedef struct {
+    int32_t nx, ny, nz;   /* cells, each >= 1                                    */
+    int32_t ntracers;     /* >= 1                                                */
+    const void* cx;       /* face Courant numbers and metric, [nz][ny][nx]       */
+    const void* cy;
+    const void* cz;       /* may be NULL                                         */
+    const void* g;
+    void* psi;            /* ntracers consecutive fields, in/out                 */
+} mpdata_batch_item;
+
+enum { MPDATA_BATCH_GRAPH = 1, MPDATA_BATCH_TUNE = 2 };
+
+size_t mpdata_batch_workspace_bytes(const mpdata_problem* common, int32_t nitems,
+                                    const mpdata_batch_item* items);
+int mpdata_run_batched(const mpdata_problem* common, int32_t nitems,
+                       const mpdata_batch_item* items, int32_t nsteps, int32_t flags,
+                       void* ws, size_t ws_bytes, void* stream);
+
 /* Mass sum(G * psi) accumulated in FP64 (compensated) for either dtype,
  * written to *host_out.  Synchronises `stream`.  ws: at least the
  * MPDATA_OP_MASS size. */

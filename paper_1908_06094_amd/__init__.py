@@ -22,7 +22,12 @@ from ._lib import (  # noqa: F401
     MPDATA_OP_RUN,
     MPDATA_OP_STEP,
     MPDATA_PERIODIC,
+    MPDATA_BATCH_GRAPH,
+    MPDATA_BATCH_TUNE,
+    BatchItem,
     MpdataError,
+    batch_problem,
+    run_batched,
     adjoint,
     mpdata_function,
     Problem,

@@ -39,6 +39,9 @@ _SIGNATURES = {
     "mpdata_mass": ([_pp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_adjoint": ([_pp, ctypes.c_int32, ctypes.c_int32] + [_vp] * 11 + [_vp, ctypes.c_size_t, _vp],
                        ctypes.c_int),
+    "mpdata_batch_workspace_bytes": ([_pp, ctypes.c_int32, _vp], ctypes.c_size_t),
+    "mpdata_run_batched": ([_pp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _vp],
+                           ctypes.c_int),
     "mpdata_last_error": ([], ctypes.c_char_p),
     "mpdata_timing_enable": ([ctypes.c_int32], ctypes.c_int),
     "mpdata_timing_read": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
@@ -242,3 +245,66 @@ def mpdata_function():
     if not _fn_cache:
         _fn_cache.append(_make_function())
     return _fn_cache[0]
+
+
+MPDATA_BATCH_GRAPH, MPDATA_BATCH_TUNE = 1, 2
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ntracers", ctypes.c_int32), ("cx", ctypes.c_void_p), ("cy", ctypes.c_void_p),
+                ("cz", ctypes.c_void_p), ("g", ctypes.c_void_p), ("psi", ctypes.c_void_p)]
+
+
+def _batch_items(problems):
+    import torch
+
+    arr = (BatchItem * len(problems))()
+    dtype = None
+    for i, pr in enumerate(problems):
+        psi, cx, cy, cz, g = pr["psi"], pr["cx"], pr["cy"], pr.get("cz"), pr["g"]
+        if psi.dim() != 4:
+            raise ValueError("psi of a batch item has shape (ntracers, nz, ny, nx)")
+        for t in (psi, cx, cy, cz, g):
+            if t is None:
+                continue
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("batch fields must be contiguous device tensors")
+            if dtype is None:
+                dtype = t.dtype
+            if t.dtype != dtype:
+                raise ValueError("all batch fields must share one dtype")
+        if tuple(cx.shape) != tuple(psi.shape[1:]) or tuple(g.shape) != tuple(psi.shape[1:]):
+            raise ValueError("winds and metric must have the shape of one tracer field")
+        nt, nz, ny, nx = psi.shape
+        arr[i] = BatchItem(nx, ny, nz, nt, cx.data_ptr(), cy.data_ptr(), 0 if cz is None else cz.data_ptr(),
+                           g.data_ptr(), psi.data_ptr())
+    return arr, {torch.float64: "f64", torch.float32: "f32"}[dtype]
+
+
+def batch_problem(problems, *, iters=2, limiter=True, bc=("periodic", "closed", "closed"), eps=0.0):
+    """(items array, common problem, workspace bytes) for run_batched."""
+    items, dt = _batch_items(problems)
+    p = problem_for((1, 1, 1), bc, iters, limiter, dt, eps)
+    nb = lib().mpdata_batch_workspace_bytes(ctypes.byref(p), len(problems), ctypes.cast(items, ctypes.c_void_p))
+    if nb == 0:
+        _check(MPDATA_EINVAL)
+    return items, p, int(nb)
+
+
+def run_batched(problems, nsteps, *, iters=2, limiter=True, bc=("periodic", "closed", "closed"), eps=0.0,
+                graph=True, tune=False, workspace=None, stream=None):
+    """nsteps steps of every problem in `problems` (dicts with psi of shape
+    (ntracers, nz, ny, nx) and cx, cy, cz (or None), g of shape (nz, ny, nx)),
+    in place, in one persistent launch per pass."""
+    import torch
+
+    items, p, nb = batch_problem(problems, iters=iters, limiter=limiter, bc=bc, eps=eps)
+    dev = problems[0]["psi"].device
+    ws = workspace if workspace is not None else _workspace(nb, dev)
+    if ws.numel() < nb:
+        raise ValueError("workspace too small")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    flags = (MPDATA_BATCH_GRAPH if graph else 0) | (MPDATA_BATCH_TUNE if tune else 0)
+    _check(lib().mpdata_run_batched(ctypes.byref(p), len(problems), ctypes.cast(items, ctypes.c_void_p),
+                                    int(nsteps), flags, _ptr(ws), ws.numel(), ctypes.c_void_p(st.cuda_stream)))

@@ -184,36 +184,19 @@ struct Raw {
     T phi, psin, u, v, w, g;
 };
 
+// March output planes [kb, ke) of one tile of one problem (all threads of
+// the workgroup call this together).
 template <class T, bool LIMIT, bool WRITE_VEL>
-__global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
+__device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
+                                             const int kb, const int ke)
 {
-    __shared__ Slots<T> S;
-
     const int lane = threadIdx.x & (kLanes - 1);
     const int row = threadIdx.x >> 6;
     const int up = row < kRows - 1 ? row + 1 : row;     // clamped: the edge rows are halo
     const int dn = row > 0 ? row - 1 : row;
     const T eps = (T)a.eps;
     const T zero = T(0);
-
-    // Work split: the (tile, output plane) pairs in tile-major order are cut
-    // into equal contiguous ranges, one per workgroup, so every workgroup
-    // marches the same number of planes (a range may span a tile boundary).
-    // Workgroups are dispatched round-robin over the 8 XCDs; consecutive
-    // ranges go to one XCD so that neighbouring tiles share its L2.
-    const int nwg = gridDim.x;                         // a multiple of 8
-    const int wg = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
-    const long long total = (long long)a.tiles_x * a.tiles_y * geo.nz;
-    const long long span = (total + nwg - 1) / nwg;
-    long long w0 = (long long)wg * span;
-    const long long w1 = w0 + span < total ? w0 + span : total;
-
-    while (w0 < w1) {
-        const int tile = (int)(w0 / geo.nz);
-        const int kb = (int)(w0 - (long long)tile * geo.nz);
-        const int ke = (int)((long long)kb + (w1 - w0) < geo.nz ? kb + (w1 - w0) : geo.nz);
-        w0 += ke - kb;
-
+    {
         const int tx = tile % a.tiles_x;
         const int ty = tile / a.tiles_x;
         const int gi = tx * kTileX - kHalo + lane;       // virtual column of this lane
@@ -391,6 +374,100 @@ __global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
             B1 = B2;
         }
         lds_barrier();   // the next segment rewrites every slot
+    }
+}
+
+// Logical workgroup id: the dispatcher deals workgroups round-robin over the
+// 8 XCDs; consecutive logical ids (hence neighbouring work) share one XCD.
+__device__ __forceinline__ int xcd_grouped_id()
+{
+    const int nwg = gridDim.x;   // a multiple of 8
+    return (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+}
+
+// One corrective pass of one problem.  Work split: the (tile, output plane)
+// pairs in tile-major order are cut into equal contiguous ranges, one per
+// workgroup, so every workgroup marches the same number of planes (a range
+// may span a tile boundary).
+template <class T, bool LIMIT, bool WRITE_VEL>
+__global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
+{
+    __shared__ Slots<T> S;
+    const int nwg = gridDim.x;
+    const int wg = xcd_grouped_id();
+    const long long total = (long long)a.tiles_x * a.tiles_y * geo.nz;
+    const long long span = (total + nwg - 1) / nwg;
+    long long w0 = (long long)wg * span;
+    const long long w1 = w0 + span < total ? w0 + span : total;
+    while (w0 < w1) {
+        const int tile = (int)(w0 / geo.nz);
+        const int kb = (int)(w0 - (long long)tile * geo.nz);
+        const int ke = (int)((long long)kb + (w1 - w0) < geo.nz ? kb + (w1 - w0) : geo.nz);
+        w0 += ke - kb;
+        pass_segment<T, LIMIT, WRITE_VEL>(geo, a, S, tile, kb, ke);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched passes: many problems (and tracers) in one launch.  Entry e covers
+// work units [begin, begin + tiles * tracers * nz) in the order (tile,
+// tracer, plane), so that the tracers of one tile, which share winds and G,
+// run on neighbouring workgroups of one XCD and share its L2.
+// ---------------------------------------------------------------------------
+template <class T>
+struct BatchEntry {
+    Geo geo;
+    PassArgs<T> args;        // tracer 0's fields; tracer t adds t * tracer_stride
+    long long begin;         // first work unit
+    long long tracer_stride; // elements between consecutive tracers' fields
+    int tracers;
+    int vel_per_tracer;      // previous velocities are per tracer (passes >= 3)
+};
+
+// WAVES_PER_SIMD: 3 = one workgroup per CU (up to 168 VGPRs per wave);
+// 6 = two workgroups per CU (the FP32 kernel's LDS allows it; VGPRs <= 80).
+template <class T, bool LIMIT, bool WRITE_VEL, int WAVES_PER_SIMD>
+__global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const BatchEntry<T>* __restrict__ tab,
+                                                                           int n_entries, long long total)
+{
+    __shared__ Slots<T> S;
+    const int nwg = gridDim.x;
+    const int wg = xcd_grouped_id();
+    const long long span = (total + nwg - 1) / nwg;
+    long long w0 = (long long)wg * span;
+    const long long w1 = w0 + span < total ? w0 + span : total;
+    while (w0 < w1) {
+        // the entry holding w0 (binary search on the begin offsets)
+        int lo = 0, hi = n_entries - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].begin <= w0) lo = mid; else hi = mid - 1;
+        }
+        const BatchEntry<T>& e = tab[lo];
+        const long long r = w0 - e.begin;
+        const long long per_tile = (long long)e.tracers * e.geo.nz;
+        const int tile = (int)(r / per_tile);
+        const long long rr = r - (long long)tile * per_tile;
+        const int tracer = (int)(rr / e.geo.nz);
+        const int kb = (int)(rr - (long long)tracer * e.geo.nz);
+        const int ke = (int)((long long)kb + (w1 - w0) < e.geo.nz ? kb + (w1 - w0) : e.geo.nz);
+        w0 += ke - kb;
+        PassArgs<T> a = e.args;
+        const long long off = (long long)tracer * e.tracer_stride;
+        a.phi += off;
+        a.psin += off;
+        a.out += off;
+        if (e.vel_per_tracer) {
+            a.u += off;
+            a.v += off;
+            if (a.w) a.w += off;
+        }
+        if (WRITE_VEL) {
+            a.ul += off;
+            a.vl += off;
+            a.wl += off;
+        }
+        pass_segment<T, LIMIT, WRITE_VEL>(e.geo, a, S, tile, kb, ke);
     }
 }
 

@@ -5,10 +5,12 @@
 // kernels of stages.hpp / fused.hpp; the host only validates and enqueues.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -19,6 +21,7 @@
 #include "stages.hpp"
 #include "fused.hpp"
 #include "adjoint.hpp"
+#include "batched.hpp"
 
 namespace {
 
@@ -151,7 +154,10 @@ struct Timed {
     Timed(int k, hipStream_t s) : kind(k), st(s)
     {
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        if (g_timing.on && (e0 = timing_event())) hipEventRecord(e0, st);
+        if (!g_timing.on) return;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
+        if ((e0 = timing_event()) && hipEventRecord(e0, st) != hipSuccess) e0 = nullptr;
     }
     ~Timed()
     {
@@ -603,6 +609,262 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// Batched driver
+// ---------------------------------------------------------------------------
+
+int validate_items(const mpdata_problem* c, int n, const mpdata_batch_item* items)
+{
+    if (n < 1) return fail(MPDATA_EINVAL, "nitems=%d must be >= 1", n);
+    if (!items) return fail(MPDATA_EINVAL, "items is NULL");
+    const size_t el = elem_size(c);
+    for (int i = 0; i < n; ++i) {
+        const mpdata_batch_item& it = items[i];
+        if (it.nx < 1 || it.ny < 1 || it.nz < 1 || it.nz > 65535 || it.ny > 65535 * 4)
+            return fail(MPDATA_EINVAL, "item %d: sizes %dx%dx%d out of range", i, it.nx, it.ny, it.nz);
+        if (it.ntracers < 1) return fail(MPDATA_EINVAL, "item %d: ntracers=%d must be >= 1", i, it.ntracers);
+        const void* req[] = {it.cx, it.cy, it.g, it.psi};
+        for (const void* q : req)
+            if (!q || !aligned(q, el)) return fail(MPDATA_EINVAL, "item %d: a required pointer is NULL or misaligned", i);
+        if (it.cz && !aligned(it.cz, el)) return fail(MPDATA_EINVAL, "item %d: cz is misaligned", i);
+    }
+    return MPDATA_OK;
+}
+
+struct BatchCacheEntry {
+    hipGraphExec_t exec = nullptr;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    int variant = -1;
+};
+
+std::mutex g_batch_mu;
+std::map<std::string, BatchCacheEntry> g_batch_cache;
+std::map<std::string, int> g_tuned;          // batch shape -> variant
+bool g_tune_file_read = false;
+hipStream_t g_capture_stream[64] = {nullptr};
+
+std::string shape_key(const mpdata_problem* c, int n, const mpdata_batch_item* items)
+{
+    std::string k;
+    char buf[96];
+    snprintf(buf, sizeof buf, "d%d i%d l%d b%d%d%d n%d", c->dtype, c->iters, c->limiter, c->bc[0], c->bc[1], c->bc[2], n);
+    k += buf;
+    for (int i = 0; i < n; ++i) {
+        snprintf(buf, sizeof buf, ";%dx%dx%dt%d%s", items[i].nx, items[i].ny, items[i].nz, items[i].ntracers,
+                 items[i].cz ? "" : "z");
+        k += buf;
+    }
+    return k;
+}
+
+void read_tune_file()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = getenv("MPDATA_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[1 << 16];
+    while (fgets(line, sizeof line, f)) {
+        char* tab = strrchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        g_tuned[line] = atoi(tab + 1);
+    }
+    fclose(f);
+}
+
+void write_tune_file(const std::string& key, int variant)
+{
+    const char* path = getenv("MPDATA_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s\t%d\n", key.c_str(), variant);
+    fclose(f);
+}
+
+template <class T>
+struct BatchDev {
+    const mpdata::stages::DonorEntry<T>* donor[2];
+    const mpdata::fused::BatchEntry<T>* pass[2][8];
+    const mpdata::stages::DonorEntry<T>* copyback;
+};
+
+template <class T>
+int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv, int par,
+                         int variant, hipStream_t st)
+{
+    const int cus = cu_count();
+    mpdata::stages::k_donor_batched<T><<<cus * 8, 256, 0, st>>>(dv.donor[par], n, tb.donor_total);
+    if (int rc = launch_status("batched donor-cell pass")) return rc;
+    for (int m = 2; m <= c->iters; ++m) {
+        const bool last = m == c->iters;
+        const mpdata::fused::BatchEntry<T>* tab = dv.pass[par][m - 2];
+        const long long total = tb.pass_total;
+        long long g1 = std::min<long long>(cus, std::max<long long>(8, (total / 12) & ~7LL));
+        g1 &= ~7LL;
+        if (g1 < 8) g1 = 8;
+        const int grid = (int)(variant == 1 ? g1 * 2 : g1);
+        Timed tm(MPDATA_KERNEL_PASS, st);
+#define MPDATA_LAUNCH(LIM, WV, OCC) \
+    mpdata::fused::k_pass_batched<T, LIM, WV, OCC><<<grid, mpdata::fused::kThreads, 0, st>>>(tab, n, total)
+        if (variant == 1) {
+            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, 6); else MPDATA_LAUNCH(true, true, 6); }
+            else { if (last) MPDATA_LAUNCH(false, false, 6); else MPDATA_LAUNCH(false, true, 6); }
+        } else {
+            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, 3); else MPDATA_LAUNCH(true, true, 3); }
+            else { if (last) MPDATA_LAUNCH(false, false, 3); else MPDATA_LAUNCH(false, true, 3); }
+        }
+#undef MPDATA_LAUNCH
+        if (int rc = launch_status("batched corrective pass")) return rc;
+    }
+    return MPDATA_OK;
+}
+
+template <class T>
+int enqueue_batched_run(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv,
+                        int nsteps, int variant, hipStream_t st)
+{
+    for (int s = 0; s < nsteps; ++s)
+        if (int rc = enqueue_batched_step<T>(c, n, tb, dv, s & 1, variant, st)) return rc;
+    if (nsteps & 1) {
+        batch::k_copy_batched<T><<<cu_count() * 8, 256, 0, st>>>(dv.copyback, n, tb.donor_total);
+        if (int rc = launch_status("batched copy-back")) return rc;
+    }
+    return MPDATA_OK;
+}
+
+template <class T>
+int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, int nsteps, int flags, void* ws,
+                hipStream_t st)
+{
+    const batch::Layout L = batch::layout(c, n, items);
+    const batch::Tables<T> tb = batch::build_tables<T>(c, n, items, L, (char*)ws);
+    // pack the tables: donor[0], donor[1], pass[0][*], pass[1][*], copyback
+    const size_t slot = std::max(sizeof(mpdata::fused::BatchEntry<double>), sizeof(mpdata::stages::DonorEntry<double>)) * n;
+    std::vector<char> host(L.table_bytes, 0);
+    BatchDev<T> dv;
+    size_t off = 0;
+    auto put = [&](const void* src, size_t bytes) {
+        memcpy(host.data() + off, src, bytes);
+        const void* dev = (const char*)ws + off;
+        off += slot;
+        return dev;
+    };
+    for (int par = 0; par < 2; ++par)
+        dv.donor[par] = (const mpdata::stages::DonorEntry<T>*)put(tb.donor[par].data(), sizeof(tb.donor[par][0]) * n);
+    for (int par = 0; par < 2; ++par)
+        for (int m = 2; m <= c->iters; ++m)
+            dv.pass[par][m - 2] =
+                (const mpdata::fused::BatchEntry<T>*)put(tb.pass[par][m - 2].data(), sizeof(tb.pass[par][0][0]) * n);
+    dv.copyback = (const mpdata::stages::DonorEntry<T>*)put(tb.copyback.data(), sizeof(tb.copyback[0]) * n);
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(MPDATA_EDEVICE, "no current device");
+    char kb[160];
+    snprintf(kb, sizeof kb, "|dev%d|ws%p|s%d|f%d", dev, ws, nsteps, flags & MPDATA_BATCH_GRAPH);
+    std::string key = shape_key(c, n, items) + kb;
+    for (int i = 0; i < n; ++i) {
+        char pb[160];
+        snprintf(pb, sizeof pb, "|%p,%p,%p,%p,%p", items[i].psi, items[i].cx, items[i].cy, items[i].cz, items[i].g);
+        key += pb;
+    }
+
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (g_batch_cache.size() >= 16 && !g_batch_cache.count(key)) {
+        // bounded cache: retire every other entry once its last upload is done
+        for (auto& kv : g_batch_cache) {
+            BatchCacheEntry& old = kv.second;
+            if (old.upload_done) {
+                (void)hipEventSynchronize(old.upload_done);
+                (void)hipEventDestroy(old.upload_done);
+            }
+            if (old.pinned) (void)hipHostFree(old.pinned);
+            if (old.exec) (void)hipGraphExecDestroy(old.exec);
+        }
+        g_batch_cache.clear();
+    }
+    BatchCacheEntry& ce = g_batch_cache[key];
+    if (!ce.pinned) {
+        if (hipHostMalloc(&ce.pinned, L.table_bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(MPDATA_EDEVICE, "pinned staging buffer for the batch tables");
+        ce.pinned_bytes = L.table_bytes;
+        if (hipEventCreateWithFlags(&ce.upload_done, hipEventDisableTiming) != hipSuccess)
+            return fail(MPDATA_EDEVICE, "event for the batch tables");
+    } else if (hipEventSynchronize(ce.upload_done) != hipSuccess) {
+        return fail(MPDATA_EDEVICE, "waiting for the previous table upload");
+    }
+    memcpy(ce.pinned, host.data(), L.table_bytes);
+    if (hipMemcpyAsync(ws, ce.pinned, L.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(ce.upload_done, st) != hipSuccess)
+        return fail(MPDATA_EDEVICE, "batch table upload");
+
+    // kernel variant: tuned (per batch shape), else one workgroup per CU
+    const std::string skey = shape_key(c, n, items);
+    read_tune_file();
+    int variant = 0;
+    auto it = g_tuned.find(skey);
+    if (it != g_tuned.end()) {
+        variant = it->second;
+    } else if ((flags & MPDATA_BATCH_TUNE) && c->dtype == MPDATA_F32) {
+        float best = 1e30f;
+        for (int v = 0; v < 2; ++v) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return fail(MPDATA_EDEVICE, "tuning events");
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2; ++rep) {   // the first is a warm-up
+                hipEventRecord(e0, st);
+                if (int rc = enqueue_batched_step<T>(c, n, tb, dv, 0, v, st)) return rc;
+                hipEventRecord(e1, st);
+                if (hipEventSynchronize(e1) != hipSuccess) return fail(MPDATA_EDEVICE, "tuning run failed");
+                hipEventElapsedTime(&ms, e0, e1);
+            }
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            if (ms < best) {
+                best = ms;
+                variant = v;
+            }
+        }
+        g_tuned[skey] = variant;
+        write_tune_file(skey, variant);
+    }
+    if (ce.variant >= 0 && ce.variant != variant && ce.exec) {
+        hipGraphExecDestroy(ce.exec);
+        ce.exec = nullptr;
+    }
+    ce.variant = variant;
+
+    if (!(flags & MPDATA_BATCH_GRAPH)) return enqueue_batched_run<T>(c, n, tb, dv, nsteps, variant, st);
+
+    if (!ce.exec) {
+        if (!g_capture_stream[dev] && hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking) != hipSuccess)
+            return fail(MPDATA_EDEVICE, "capture stream");
+        hipStream_t cs = g_capture_stream[dev];
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(MPDATA_EDEVICE, "graph capture could not start");
+        int rc = enqueue_batched_run<T>(c, n, tb, dv, nsteps, variant, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess || !graph) return fail(MPDATA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&ce.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(MPDATA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipGraphLaunch(ce.exec, st);
+    if (e != hipSuccess) return fail(MPDATA_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -740,6 +1002,36 @@ int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_e
     return adjoint_run(p, nsteps, K, (const double*)psi0, (const double*)cx, (const double*)cy, (const double*)cz,
                        (const double*)g, (const double*)dJ_dpsiT, (double*)dJ_dpsi0, (double*)dJ_dcx,
                        (double*)dJ_dcy, (double*)dJ_dcz, (double*)psiT_out, ws, (hipStream_t)stream);
+}
+
+size_t mpdata_batch_workspace_bytes(const mpdata_problem* common, int32_t nitems, const mpdata_batch_item* items)
+{
+    if (!common) { fail(MPDATA_EINVAL, "problem pointer is NULL"); return 0; }
+    mpdata_problem c = *common;
+    c.nx = c.ny = c.nz = 1;
+    if (validate(&c) != MPDATA_OK) return 0;
+    if (validate_items(&c, nitems, items) != MPDATA_OK) return 0;
+    return batch::layout(&c, nitems, items).total;
+}
+
+int mpdata_run_batched(const mpdata_problem* common, int32_t nitems, const mpdata_batch_item* items,
+                       int32_t nsteps, int32_t flags, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!common) return fail(MPDATA_EINVAL, "problem pointer is NULL");
+    mpdata_problem c = *common;
+    c.nx = c.ny = c.nz = 1;   // sizes come from the items
+    if (int rc = validate(&c)) return rc;
+    if (int rc = validate_items(&c, nitems, items)) return rc;
+    if (nsteps < 0) return fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps);
+    if (flags & ~(MPDATA_BATCH_GRAPH | MPDATA_BATCH_TUNE)) return fail(MPDATA_EINVAL, "unknown flags 0x%x", flags);
+    if (c.iters > 9) return fail(MPDATA_EUNSUPPORTED, "batched runs support up to 9 passes");
+    if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
+    const batch::Layout L = batch::layout(&c, nitems, items);
+    if (ws_bytes < L.total)
+        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the batch needs", ws_bytes, L.total);
+    if (nsteps == 0) return ok();
+    if (c.dtype == MPDATA_F64) return run_batched<double>(&c, nitems, items, nsteps, flags, ws, (hipStream_t)stream);
+    return run_batched<float>(&c, nitems, items, nsteps, flags, ws, (hipStream_t)stream);
 }
 
 int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g, double* host_out, void* ws,

@@ -67,14 +67,12 @@ __device__ __forceinline__ int closed(const Geo& g, int axis)
     return axis == 0 ? g.closed_x : axis == 1 ? g.closed_y : g.closed_z;
 }
 
-// Donor-cell pass: out = phi - div(F)/G with F = [u]+ phi_left + [u]- phi_right.
+// Donor-cell update of one cell: phi - div(F)/G with F = [u]+ phi_left + [u]- phi_right.
 template <class T>
-__global__ void __launch_bounds__(256) k_donor(Geo g, const T* __restrict__ phi, const T* __restrict__ u,
-                                               const T* __restrict__ v, const T* __restrict__ w,
-                                               const T* __restrict__ gm, T* __restrict__ out)
+__device__ __forceinline__ T donor_cell(const Geo& g, const Cell& c, const T* __restrict__ phi,
+                                        const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+                                        const T* __restrict__ gm)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     const T* vel[3] = {u, v, w};
     const T pc = phi[c.q];
     T dif[3];
@@ -95,7 +93,57 @@ __global__ void __launch_bounds__(256) k_donor(Geo g, const T* __restrict__ phi,
         T fl = (pos_part(ul) * pl) + (neg_part(ul) * pc);
         dif[a] = fr - fl;
     }
-    out[c.q] = pc - ((dif[0] + dif[1]) + dif[2]) / gm[c.q];
+    return pc - ((dif[0] + dif[1]) + dif[2]) / gm[c.q];
+}
+
+// Donor-cell pass over one problem.
+template <class T>
+__global__ void __launch_bounds__(256) k_donor(Geo g, const T* __restrict__ phi, const T* __restrict__ u,
+                                               const T* __restrict__ v, const T* __restrict__ w,
+                                               const T* __restrict__ gm, T* __restrict__ out)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    out[c.q] = donor_cell(g, c, phi, u, v, w, gm);
+}
+
+// Donor-cell pass over many problems and tracers (one launch): entry e owns
+// the global cells [begin, begin + tracers * cells).
+template <class T>
+struct DonorEntry {
+    Geo geo;
+    const T* phi;      // tracer 0 (tracer t at + t * stride)
+    T* out;
+    const T* u;
+    const T* v;
+    const T* w;        // may be NULL
+    const T* g;
+    long long begin, cells, stride;
+    int tracers;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_donor_batched(const DonorEntry<T>* __restrict__ tab, int n_entries,
+                                                       long long total)
+{
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += step) {
+        int lo = 0, hi = n_entries - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].begin <= idx) lo = mid; else hi = mid - 1;
+        }
+        const DonorEntry<T>& e = tab[lo];
+        const long long r = idx - e.begin;
+        const long long tr = r / e.cells;
+        Cell c;
+        c.q = r - tr * e.cells;
+        c.k = (int)(c.q / e.geo.sz);
+        c.j = (int)((c.q - (long long)c.k * e.geo.sz) / e.geo.sy);
+        c.i = (int)(c.q - (long long)c.k * e.geo.sz - (long long)c.j * e.geo.sy);
+        const long long off = tr * e.stride;
+        e.out[off + c.q] = donor_cell(e.geo, c, e.phi + off, e.u, e.v, e.w, e.g);
+    }
 }
 
 // Antidiffusive pseudo-velocities at the three own faces of every cell.

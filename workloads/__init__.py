@@ -203,6 +203,22 @@ def config5_weights(shape, seed=5):
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=shape)
 
 
+def config4(count=64, seed=4, dtype=np.float32, max_courant=0.5):
+    """Batched workload: `count` lat-lon problems of uneven sizes, each with
+    1-8 lognormal(0, 1) tracers sharing its winds (config-3 streamfunction
+    family at max Courant 0.5) and metric; FP32, 2 passes, limiter, 20 steps.
+    Returns a list of dicts: psi (ntracers, nz, ny, nx), cx, cy, cz, g."""
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    for nx, ny, nz, nt in batched_problems(count, seed):
+        cx, cy, cz, _ = stream_winds(nx, ny, nz, "wave", max_courant)
+        g = metric(nx, ny, nz)
+        psi = np.exp(rng.standard_normal((nt, nz, ny, nx), dtype=np.float64)).astype(dtype)
+        out.append({"psi": psi, "cx": cx.astype(dtype), "cy": cy.astype(dtype), "cz": cz.astype(dtype),
+                    "g": g.astype(dtype)})
+    return out
+
+
 def batched_problems(count=64, seed=4):
     """Sizes and tracer counts of the batched workload: nx in U{64..512},
     ny in U{32..256}, nz in U{20..80}, 1-8 tracers."""
