@@ -143,6 +143,42 @@ def time_adjoint(mp, torch, dev, steps=20, checkpoint_every=5, reps=3):
             "forward_ms": round(f * 1e3, 3), "adjoint_ms": round(a * 1e3, 3), "ratio": round(a / f, 2)}
 
 
+def time_batched(mp, torch, dev, steps=20, reps=3):
+    """The batched workload: 64 lat-lon problems of uneven sizes with 1-8
+    tracers each (FP32, 2 passes, limiter), 20 steps per call, one persistent
+    launch per pass, replayed from a captured HIP graph (autotuned variant)."""
+    import numpy as np
+
+    import workloads
+
+    probs_h = workloads.config4()
+    probs = [{k: torch.from_numpy(v).to(dev) for k, v in p.items()} for p in probs_h]
+    del probs_h
+    start = [p["psi"].clone() for p in probs]
+    tracer_cells = sum(p["psi"].numel() for p in probs)
+    _, _, nb = mp.batch_problem(probs, iters=2)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(stream):
+        mp.run_batched(probs, steps, iters=2, graph=True, tune=True, workspace=ws, stream=stream)  # tune + capture
+        stream.synchronize()
+        times = []
+        for _ in range(reps):
+            for p, s0 in zip(probs, start):
+                p["psi"].copy_(s0)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            mp.run_batched(probs, steps, iters=2, graph=True, tune=True, workspace=ws, stream=stream)
+            stream.synchronize()
+            times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    log(f"[bench] batched: {tracer_cells / 1e6:.0f} M tracer-cells x {steps} steps in {t * 1e3:.1f} ms")
+    return {"workload": f"64 lat-lon problems (nx 64-512, ny 32-256, nz 20-80), 1-8 tracers, FP32, 2 passes, "
+                        f"limiter, {steps} steps, HIP graph",
+            "tracer_cells": tracer_cells, "value": round(tracer_cells * steps / t, 1),
+            "unit": "tracer-cell updates/s", "ms_per_step": round(t * 1e3 / steps, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched 64-problem FP32 measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward timing on the 256x128x60 workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -216,6 +254,9 @@ def main():
     adjoint = None
     if not args.no_adjoint and args.dtype == "f64":
         adjoint = time_adjoint(mp, torch, dev)
+    batched = None
+    if not args.no_batched:
+        batched = time_batched(mp, torch, dev)
 
     if args.copy_calibration:
         src = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
@@ -272,6 +313,7 @@ def main():
                  "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
         "cpu_baseline": cpu,
         "adjoint": adjoint,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

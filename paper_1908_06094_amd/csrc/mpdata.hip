@@ -302,7 +302,8 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     T* first_out = p->iters == 1 ? psout : b.phi[0];
     {
         Timed tm(MPDATA_KERNEL_DONOR, st);
-        mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+        dim3 dgrd((p->nx + 63) / 64, (p->ny + 3) / 4, (p->nz + mpdata::fused::kDonorChunk - 1) / mpdata::fused::kDonorChunk);
+        mpdata::fused::k_donor_march<T><<<dgrd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
     }
     if (int rc = launch_status("donor-cell pass")) return rc;
 
