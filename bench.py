@@ -66,19 +66,10 @@ def traffic_record(kernel_src_sha, dtype):
     return rec.get("bytes_per_launch")
 
 
-def kernel_source_sha():
-    import hashlib
-
-    h = hashlib.sha256()
-    for name in ("fused.hpp", "common.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1908_06094_amd", "csrc", name), "rb").read())
-    return h.hexdigest()
-
-
 def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
     """Roofline of the dominant kernel: the fused corrective pass (or, on the
     per-stage path, all stage kernels of a step taken together)."""
-    from paper_1908_06094_amd import model
+    from paper_1908_06094_amd import model, profsum
 
     with_cz = True
     if pass_n:
@@ -88,7 +79,7 @@ def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
         avg_s = pass_ms * 1e-3 / pass_n
         ops = model.corrective_pass_ops(w.limiter)
         kernel = "fused corrective pass (k_pass)"
-        traffic = traffic_record(kernel_source_sha(), dtype)
+        traffic = traffic_record(profsum.kernel_source_sha(), dtype)
     else:
         bytes_per_launch = bytes_per_cell_step(elem) * w.cells
         avg_s = stage_ms * 1e-3 / max(stage_n, 1) if stage_n else ev_ms * 1e-3 / steps

@@ -25,6 +25,7 @@
 
 #include "mpdata.h"
 #include "fused.hpp"
+#include "donor.hpp"
 #include "stages.hpp"
 
 namespace batch {
@@ -58,7 +59,8 @@ inline Layout layout(const mpdata_problem* c, int n, const mpdata_batch_item* it
     L.n = n;
     L.iters = c->iters;
     L.fields_per_tracer = 3 + (c->iters >= 3 ? 6 : 0);
-    const size_t entry = std::max(sizeof(BatchEntry<double>), sizeof(DonorEntry<double>));
+    const size_t entry = std::max(sizeof(BatchEntry<double>),
+                                  std::max(sizeof(DonorEntry<double>), sizeof(mpdata::fused::DonorBlocks<double>)));
     L.table_bytes = align256((size_t)tables_count(c->iters) * n * entry);
     size_t off = L.table_bytes;
     for (int i = 0; i < n; ++i) {
@@ -104,10 +106,10 @@ inline Geo geo_of_item(const mpdata_problem* c, const mpdata_batch_item& it)
 // Host copies of every table (uploaded once per call, ahead of the launches).
 template <class T>
 struct Tables {
-    std::vector<DonorEntry<T>> donor[2];                // by step parity
+    std::vector<mpdata::fused::DonorBlocks<T>> donor[2];  // by step parity
     std::vector<std::vector<BatchEntry<T>>> pass[2];    // [parity][m - 2]
     std::vector<DonorEntry<T>> copyback;                // S -> user (odd step counts)
-    long long donor_total = 0, pass_total = 0;
+    long long donor_total = 0, pass_total = 0, donor_blocks = 0;
 };
 
 template <class T>
@@ -117,18 +119,18 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
     const int M = c->iters;
     const double eps = c->eps > 0.0 ? c->eps : 1e-15;
     for (int par = 0; par < 2; ++par) tb.pass[par].resize(M > 1 ? M - 1 : 0);
-    long long dbeg = 0, pbeg = 0;
+    long long dbeg = 0, pbeg = 0, bbeg = 0;
     for (int i = 0; i < n; ++i) {
         const mpdata_batch_item& it = items[i];
         const ItemPtrs<T> P = item_ptrs<T>(L, ws, it, i);
         const Geo g = geo_of_item(c, it);
         const long long cells = L.cells[i];
-        const int tiles = ((it.nx + mpdata::fused::kTileX - 1) / mpdata::fused::kTileX) *
-                          ((it.ny + mpdata::fused::kTileY - 1) / mpdata::fused::kTileY);
+        const int tiles = ((it.nx + mpdata::fused::Tile<T>::tile_x - 1) / mpdata::fused::Tile<T>::tile_x) *
+                          ((it.ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y);
         for (int par = 0; par < 2; ++par) {
             T* src = par == 0 ? P.user : P.f[2];
             T* dst = par == 0 ? P.f[2] : P.user;
-            DonorEntry<T> d;
+            mpdata::fused::DonorBlocks<T> d;
             d.geo = g;
             d.phi = src;
             d.out = M == 1 ? dst : P.f[0];
@@ -136,9 +138,11 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
             d.v = (const T*)it.cy;
             d.w = (const T*)it.cz;
             d.g = (const T*)it.g;
-            d.begin = dbeg;
-            d.cells = cells;
             d.stride = cells;
+            d.block_begin = bbeg;
+            d.bx = (it.nx + 63) / 64;
+            d.by = (it.ny + 3) / 4;
+            d.bz = (it.nz + mpdata::fused::kDonorChunk - 1) / mpdata::fused::kDonorChunk;
             d.tracers = it.ntracers;
             tb.donor[par].push_back(d);
             for (int m = 2; m <= M; ++m) {
@@ -164,8 +168,8 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
                 a.wl = m < M ? vout[2] : nullptr;
                 a.g = (const T*)it.g;
                 a.eps = eps;
-                a.tiles_x = (it.nx + mpdata::fused::kTileX - 1) / mpdata::fused::kTileX;
-                a.tiles_y = (it.ny + mpdata::fused::kTileY - 1) / mpdata::fused::kTileY;
+                a.tiles_x = (it.nx + mpdata::fused::Tile<T>::tile_x - 1) / mpdata::fused::Tile<T>::tile_x;
+                a.tiles_y = (it.ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y;
                 e.begin = pbeg;
                 e.tracer_stride = cells;
                 e.tracers = it.ntracers;
@@ -173,14 +177,23 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
                 tb.pass[par][m - 2].push_back(e);
             }
         }
-        DonorEntry<T> cb = tb.donor[1].back();
+        DonorEntry<T> cb;
+        cb.geo = g;
         cb.phi = P.f[2];
         cb.out = P.user;
+        cb.u = cb.v = cb.w = cb.g = nullptr;
+        cb.begin = dbeg;
+        cb.cells = cells;
+        cb.stride = cells;
+        cb.tracers = it.ntracers;
         tb.copyback.push_back(cb);
+        const mpdata::fused::DonorBlocks<T>& d0 = tb.donor[0].back();
+        bbeg += (long long)d0.bx * d0.by * d0.bz * it.ntracers;
         dbeg += cells * it.ntracers;
         pbeg += (long long)tiles * it.ntracers * it.nz;
     }
     tb.donor_total = dbeg;
+    tb.donor_blocks = bbeg;
     tb.pass_total = pbeg;
     return tb;
 }

@@ -37,20 +37,34 @@
 namespace mpdata {
 namespace fused {
 
-constexpr int kLanes = 64;               // x extent of a tile, halo included
-constexpr int kRows = 12;                // y extent (waves per workgroup)
+#ifndef MPDATA_ROW_LANES_F64
+#define MPDATA_ROW_LANES_F64 64
+#endif
+#ifndef MPDATA_ROW_LANES_F32
+#define MPDATA_ROW_LANES_F32 32
+#endif
+constexpr int kThreads = 768;                // 12 waves: 3 per SIMD, up to 168 VGPRs each
 constexpr int kHalo = 2;
-constexpr int kTileX = kLanes - 2 * kHalo;   // 60 interior columns
-constexpr int kTileY = kRows - 2 * kHalo;    // 8 interior rows
-constexpr int kThreads = kLanes * kRows;     // 768: 3 waves per SIMD, up to 168 VGPRs each
+
+// Tile shape per element type: a tile row is `lanes` wide (a wave holds
+// 64 / lanes rows) and the workgroup's 768 threads hold `rows` rows.
+template <class T>
+struct Tile {
+    static constexpr int lanes = sizeof(T) == 8 ? MPDATA_ROW_LANES_F64 : MPDATA_ROW_LANES_F32;
+    static constexpr int shift = lanes == 64 ? 6 : (lanes == 32 ? 5 : 4);
+    static constexpr int rows = kThreads / lanes;
+    static constexpr int tile_x = lanes - 2 * kHalo;   // interior columns
+    static constexpr int tile_y = rows - 2 * kHalo;    // interior rows
+    static_assert((1 << shift) == lanes && lanes >= 16 && lanes <= 64, "a tile row is 16, 32 or 64 lanes");
+};
 
 // ---------------------------------------------------------------------------
 // Lane shifts.  next(v): lane l receives lane l+1's value; prev(v): lane l-1's.
-// The lane without a source receives 0 (it lies in the halo that the shrinking
-// valid region discards).
+// The lane without a source reads 0 (bound_ctrl; it lies in the halo that the
+// shrinking valid region discards), so the destination needs no initial value.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
 
 __device__ __forceinline__ double lane_next(double v)
 {
@@ -119,6 +133,10 @@ __device__ __forceinline__ float fmx(float a, float b) { return __builtin_fmaxf(
 __device__ __forceinline__ float fmn(float a, float b) { return __builtin_fminf(a, b); }
 template <class T> __device__ __forceinline__ T min3(T a, T b, T c) { return fmn(a, fmn(b, c)); }
 
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): wait for
+// every vector memory operation of this wave.
+__device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Workgroup barrier ordering LDS only: prefetched global loads stay in flight.
 __device__ __forceinline__ void lds_barrier()
 {
@@ -160,6 +178,7 @@ __device__ __forceinline__ bool wall_face(int x, int n, int closed) { return clo
 
 template <class T>
 struct Slots {
+    static constexpr int kRows = Tile<T>::rows, kLanes = Tile<T>::lanes;
     // y-exchange planes, one value per (row, lane); phi, px and vpx keep the
     // last two planes (slot = plane parity) so that plane k's neighbours are
     // read one march step after they were published
@@ -190,8 +209,10 @@ template <class T, bool LIMIT, bool WRITE_VEL>
 __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
                                              const int kb, const int ke)
 {
+    constexpr int kLanes = Tile<T>::lanes, kRows = Tile<T>::rows;
+    constexpr int kTileX = Tile<T>::tile_x, kTileY = Tile<T>::tile_y;
     const int lane = threadIdx.x & (kLanes - 1);
-    const int row = threadIdx.x >> 6;
+    const int row = threadIdx.x >> Tile<T>::shift;
     const int up = row < kRows - 1 ? row + 1 : row;     // clamped: the edge rows are halo
     const int dn = row > 0 ? row - 1 : row;
     const T eps = (T)a.eps;
@@ -209,15 +230,20 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
 
-        // plane loader: cell quantities through the halo rule, faces masked at walls
+        // plane loader: cell quantities through the halo rule.  Every load is
+        // issued unconditionally and the wall masks are applied where the
+        // plane is consumed (one march step later), so nothing waits for a
+        // prefetch on the step that issues it.
+        const bool has_w = a.w != nullptr;
+        const T* wsrc = has_w ? a.w : a.g;
         auto load = [&](int k, Raw<T>& B) __attribute__((always_inline)) {
             const int ck = map_index(k, geo.nz, geo.closed_z);
             const long long q = (long long)ck * geo.sz + col;
             B.phi = a.phi[q];
-            B.psin = LIMIT ? a.psin[q] : zero;
-            B.u = xwall ? zero : a.u[q];
-            B.v = ywall ? zero : a.v[q];
-            B.w = (a.w == nullptr || wall_face(k, geo.nz, geo.closed_z)) ? zero : a.w[q];
+            if (LIMIT) B.psin = a.psin[q];
+            B.u = a.u[q];
+            B.v = a.v[q];
+            B.w = wsrc[q];
             B.g = a.g[q];
         };
 
@@ -230,17 +256,38 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         T fz_pp = 0;                // z flux at face k-3/2
         const int t_last = ke + 1;
 
+        // Results of march step t (plane t-2 and the velocities of plane
+        // t-1) are stored at the start of step t+1, before that step's
+        // prefetch: waiting for a prefetch then never waits for a store.
+        T st_upd = 0, st_ulz = 0, st_ulx = 0, st_uly = 0;
+        auto flush = [&](const int t) __attribute__((always_inline)) {
+            const int ko = t - 2;
+            const long long q0 = (long long)ko * geo.sz + col;
+            if (writer && ko >= kb && ko < ke) {
+                a.out[q0] = st_upd;
+                if (WRITE_VEL) a.wl[q0] = st_ulz;   // face (k-1)+1/2
+            }
+            if (WRITE_VEL && writer && ko + 1 >= kb && ko + 1 < ke) {
+                a.ul[q0 + geo.sz] = st_ulx;          // plane k
+                a.vl[q0 + geo.sz] = st_uly;
+            }
+        };
+
         // March step t: plane t (bank N) has arrived; velocities and beta of
         // plane k = t-1 (bank C) are formed, and plane k-1 (bank P) is updated.
         auto step = [&](const int t, Bank<T>& P, Bank<T>& C, Bank<T>& N) __attribute__((always_inline)) {
+            // the prefetch of plane t and the previous step's stores, both
+            // issued one step ago, have landed: every later wait is free
+            vmem_wait_all();
+            flush(t - 1);
             // ---------------- phase 0: plane t arrives ----------------
             N.phi = R.phi;
-            N.u = R.u;
-            N.v = R.v;
-            N.w = R.w;
+            N.u = xwall ? zero : R.u;
+            N.v = ywall ? zero : R.v;
+            N.w = (!has_w || wall_face(t, geo.nz, geo.closed_z)) ? zero : R.w;
             N.g = R.g;
             const T psin_n = R.psin;
-            if (t + 1 <= t_last) load(t + 1, R);    // prefetch the next plane
+            load(t + 1 <= t_last ? t + 1 : t_last, R);   // prefetch the next plane (unconditionally)
             const int sn = t & 1, sc = sn ^ 1;      // ring slots of planes t (= k+1) and k
             N.px = lane_next(N.phi) + N.phi;
             N.vpx = N.v + lane_next(N.v);
@@ -345,18 +392,11 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
             const T fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
             const T fy_p_dn = S.fy[par ^ 1][dn][lane];
             const T fx_p_l = lane_prev(fx_p);      // every lane: DPP needs its source lanes active
-            const int ko = t - 2;                  // plane k-1
-            if (writer && ko >= kb && ko < ke) {
-                const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
-                const long long q = (long long)ko * geo.sz + col;
-                a.out[q] = P.phi - div / P.g;
-                if (WRITE_VEL) a.wl[q] = ulz;      // face (k-1)+1/2
-            }
-            if (WRITE_VEL && writer && ko + 1 >= kb && ko + 1 < ke) {
-                const long long q = (long long)(ko + 1) * geo.sz + col;   // plane k
-                a.ul[q] = ulx;
-                a.vl[q] = uly;
-            }
+            const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
+            st_upd = P.phi - div / P.g;            // plane k-1, stored by the next step
+            st_ulz = ulz;
+            st_ulx = ulx;
+            st_uly = uly;
             fz_pp = fz_h;
             wsx = N.wpx + C.wpx;
             wsy = N.wpy + C.wpy;
@@ -373,61 +413,8 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
             B0 = B1;
             B1 = B2;
         }
+        flush(t_last);
         lds_barrier();   // the next segment rewrites every slot
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Donor-cell pass of the fast path: one thread per (i, j) column marching a
-// chunk of levels; psi at k-1, k, k+1 and w at k-1/2 stay in registers, the
-// x and y neighbours come through L1/L2.  HBM traffic: read psi, Cx, Cy, Cz,
-// G and write psi^(1), once per cell.
-// ---------------------------------------------------------------------------
-constexpr int kDonorChunk = 16;
-
-template <class T>
-__global__ void __launch_bounds__(256) k_donor_march(Geo g, const T* __restrict__ phi, const T* __restrict__ u,
-                                                     const T* __restrict__ v, const T* __restrict__ w,
-                                                     const T* __restrict__ gm, T* __restrict__ out)
-{
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
-    const int k0 = blockIdx.z * kDonorChunk;
-    const int k1 = k0 + kDonorChunk < g.nz ? k0 + kDonorChunk : g.nz;
-    const long long col = (long long)j * g.sy + i;
-    const long long c_im = (long long)j * g.sy + map_index(i - 1, g.nx, g.closed_x);
-    const long long c_ip = (long long)j * g.sy + map_index(i + 1, g.nx, g.closed_x);
-    const long long c_jm = (long long)map_index(j - 1, g.ny, g.closed_y) * g.sy + i;
-    const long long c_jp = (long long)map_index(j + 1, g.ny, g.closed_y) * g.sy + i;
-    // the face left of / below the cell: slot i-1 (wrapping) unless it is a wall
-    const bool xr = !wall_face(i, g.nx, g.closed_x), xl = !wall_face(i - 1, g.nx, g.closed_x);
-    const bool yr = !wall_face(j, g.ny, g.closed_y), yl = !wall_face(j - 1, g.ny, g.closed_y);
-    const long long f_xl = (long long)j * g.sy + (i == 0 ? g.nx - 1 : i - 1);
-    const long long f_yl = (long long)(j == 0 ? g.ny - 1 : j - 1) * g.sy + i;
-    const T zero = T(0);
-
-    auto plane = [&](int k) { return (long long)map_index(k, g.nz, g.closed_z) * g.sz; };
-    auto wface = [&](int k) { return (w == nullptr || wall_face(k, g.nz, g.closed_z)) ? zero : w[plane(k) + col]; };
-    T p_m = phi[plane(k0 - 1) + col];
-    T p_c = phi[plane(k0) + col];
-    T w_m = wface(k0 - 1);
-    for (int k = k0; k < k1; ++k) {
-        const long long b = (long long)k * g.sz;
-        const T p_p = phi[plane(k + 1) + col];
-        const T w_c = wface(k);
-        const T ur = xr ? u[b + col] : zero, ul = xl ? u[b + f_xl] : zero;
-        const T vr = yr ? v[b + col] : zero, vl = yl ? v[b + f_yl] : zero;
-        const T fxr = pos_f(ur) * p_c + neg_f(ur) * phi[b + c_ip];
-        const T fxl = pos_f(ul) * phi[b + c_im] + neg_f(ul) * p_c;
-        const T fyr = pos_f(vr) * p_c + neg_f(vr) * phi[b + c_jp];
-        const T fyl = pos_f(vl) * phi[b + c_jm] + neg_f(vl) * p_c;
-        const T fzr = pos_f(w_c) * p_c + neg_f(w_c) * p_p;
-        const T fzl = pos_f(w_m) * p_m + neg_f(w_m) * p_c;
-        out[b + col] = p_c - (((fxr - fxl) + (fyr - fyl)) + (fzr - fzl)) / gm[b + col];
-        p_m = p_c;
-        p_c = p_p;
-        w_m = w_c;
     }
 }
 

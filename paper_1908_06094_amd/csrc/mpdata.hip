@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "stages.hpp"
 #include "fused.hpp"
+#include "donor.hpp"
 #include "adjoint.hpp"
 #include "batched.hpp"
 
@@ -311,8 +312,8 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     a.psin = psin;
     a.g = gm;
     a.eps = p->eps > 0.0 ? p->eps : 1e-15;
-    a.tiles_x = (p->nx + mpdata::fused::kTileX - 1) / mpdata::fused::kTileX;
-    a.tiles_y = (p->ny + mpdata::fused::kTileY - 1) / mpdata::fused::kTileY;
+    a.tiles_x = (p->nx + mpdata::fused::Tile<T>::tile_x - 1) / mpdata::fused::Tile<T>::tile_x;
+    a.tiles_y = (p->ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y;
     a.u = cx;
     a.v = cy;
     a.w = cz;
@@ -619,6 +620,7 @@ int validate_items(const mpdata_problem* c, int n, const mpdata_batch_item* item
     if (n < 1) return fail(MPDATA_EINVAL, "nitems=%d must be >= 1", n);
     if (!items) return fail(MPDATA_EINVAL, "items is NULL");
     const size_t el = elem_size(c);
+    long long donor_blocks = 0;
     for (int i = 0; i < n; ++i) {
         const mpdata_batch_item& it = items[i];
         if (it.nx < 1 || it.ny < 1 || it.nz < 1 || it.nz > 65535 || it.ny > 65535 * 4)
@@ -628,6 +630,9 @@ int validate_items(const mpdata_problem* c, int n, const mpdata_batch_item* item
         for (const void* q : req)
             if (!q || !aligned(q, el)) return fail(MPDATA_EINVAL, "item %d: a required pointer is NULL or misaligned", i);
         if (it.cz && !aligned(it.cz, el)) return fail(MPDATA_EINVAL, "item %d: cz is misaligned", i);
+        donor_blocks += (long long)((it.nx + 63) / 64) * ((it.ny + 3) / 4) *
+                        ((it.nz + mpdata::fused::kDonorChunk - 1) / mpdata::fused::kDonorChunk) * it.ntracers;
+        if (donor_blocks > 0x7fffffffLL) return fail(MPDATA_EINVAL, "the batch exceeds 2^31-1 donor-pass blocks");
     }
     return MPDATA_OK;
 }
@@ -690,7 +695,7 @@ void write_tune_file(const std::string& key, int variant)
 
 template <class T>
 struct BatchDev {
-    const mpdata::stages::DonorEntry<T>* donor[2];
+    const mpdata::fused::DonorBlocks<T>* donor[2];
     const mpdata::fused::BatchEntry<T>* pass[2][8];
     const mpdata::stages::DonorEntry<T>* copyback;
 };
@@ -700,8 +705,14 @@ int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>&
                          int variant, hipStream_t st)
 {
     const int cus = cu_count();
-    mpdata::stages::k_donor_batched<T><<<cus * 8, 256, 0, st>>>(dv.donor[par], n, tb.donor_total);
+    {
+        Timed td(MPDATA_KERNEL_DONOR, st);
+        mpdata::fused::k_donor_march_batched<T><<<(unsigned)tb.donor_blocks, 256, 0, st>>>(dv.donor[par], n);
+    }
     if (int rc = launch_status("batched donor-cell pass")) return rc;
+    // two workgroups per CU only fit the LDS in single precision
+    constexpr int kOcc2 = sizeof(T) == 4 ? 6 : 3;
+    if (sizeof(T) != 4) variant = 0;
     for (int m = 2; m <= c->iters; ++m) {
         const bool last = m == c->iters;
         const mpdata::fused::BatchEntry<T>* tab = dv.pass[par][m - 2];
@@ -714,8 +725,8 @@ int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>&
 #define MPDATA_LAUNCH(LIM, WV, OCC) \
     mpdata::fused::k_pass_batched<T, LIM, WV, OCC><<<grid, mpdata::fused::kThreads, 0, st>>>(tab, n, total)
         if (variant == 1) {
-            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, 6); else MPDATA_LAUNCH(true, true, 6); }
-            else { if (last) MPDATA_LAUNCH(false, false, 6); else MPDATA_LAUNCH(false, true, 6); }
+            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, kOcc2); else MPDATA_LAUNCH(true, true, kOcc2); }
+            else { if (last) MPDATA_LAUNCH(false, false, kOcc2); else MPDATA_LAUNCH(false, true, kOcc2); }
         } else {
             if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, 3); else MPDATA_LAUNCH(true, true, 3); }
             else { if (last) MPDATA_LAUNCH(false, false, 3); else MPDATA_LAUNCH(false, true, 3); }
@@ -746,7 +757,9 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
     const batch::Layout L = batch::layout(c, n, items);
     const batch::Tables<T> tb = batch::build_tables<T>(c, n, items, L, (char*)ws);
     // pack the tables: donor[0], donor[1], pass[0][*], pass[1][*], copyback
-    const size_t slot = std::max(sizeof(mpdata::fused::BatchEntry<double>), sizeof(mpdata::stages::DonorEntry<double>)) * n;
+    const size_t slot = std::max(sizeof(mpdata::fused::BatchEntry<double>),
+                                 std::max(sizeof(mpdata::stages::DonorEntry<double>),
+                                          sizeof(mpdata::fused::DonorBlocks<double>))) * n;
     std::vector<char> host(L.table_bytes, 0);
     BatchDev<T> dv;
     size_t off = 0;
@@ -757,7 +770,7 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
         return dev;
     };
     for (int par = 0; par < 2; ++par)
-        dv.donor[par] = (const mpdata::stages::DonorEntry<T>*)put(tb.donor[par].data(), sizeof(tb.donor[par][0]) * n);
+        dv.donor[par] = (const mpdata::fused::DonorBlocks<T>*)put(tb.donor[par].data(), sizeof(tb.donor[par][0]) * n);
     for (int par = 0; par < 2; ++par)
         for (int m = 2; m <= c->iters; ++m)
             dv.pass[par][m - 2] =
@@ -812,21 +825,26 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
     if (it != g_tuned.end()) {
         variant = it->second;
     } else if ((flags & MPDATA_BATCH_TUNE) && c->dtype == MPDATA_F32) {
+        struct Events {
+            hipEvent_t e[2] = {nullptr, nullptr};
+            ~Events()
+            {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } ev;
+        if (hipEventCreate(&ev.e[0]) != hipSuccess || hipEventCreate(&ev.e[1]) != hipSuccess)
+            return fail(MPDATA_EDEVICE, "tuning events");
         float best = 1e30f;
         for (int v = 0; v < 2; ++v) {
-            hipEvent_t e0, e1;
-            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-                return fail(MPDATA_EDEVICE, "tuning events");
             float ms = 0.0f;
             for (int rep = 0; rep < 2; ++rep) {   // the first is a warm-up
-                hipEventRecord(e0, st);
+                if (hipEventRecord(ev.e[0], st) != hipSuccess) return fail(MPDATA_EDEVICE, "tuning event record");
                 if (int rc = enqueue_batched_step<T>(c, n, tb, dv, 0, v, st)) return rc;
-                hipEventRecord(e1, st);
-                if (hipEventSynchronize(e1) != hipSuccess) return fail(MPDATA_EDEVICE, "tuning run failed");
-                hipEventElapsedTime(&ms, e0, e1);
+                if (hipEventRecord(ev.e[1], st) != hipSuccess || hipEventSynchronize(ev.e[1]) != hipSuccess ||
+                    hipEventElapsedTime(&ms, ev.e[0], ev.e[1]) != hipSuccess)
+                    return fail(MPDATA_EDEVICE, "tuning run failed");
             }
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
             if (ms < best) {
                 best = ms;
                 variant = v;
@@ -836,7 +854,7 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
         write_tune_file(skey, variant);
     }
     if (ce.variant >= 0 && ce.variant != variant && ce.exec) {
-        hipGraphExecDestroy(ce.exec);
+        (void)hipGraphExecDestroy(ce.exec);
         ce.exec = nullptr;
     }
     ce.variant = variant;
@@ -853,12 +871,12 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &graph);
         if (rc) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return rc;
         }
         if (e != hipSuccess || !graph) return fail(MPDATA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&ce.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(MPDATA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
     hipError_t e = hipGraphLaunch(ce.exec, st);

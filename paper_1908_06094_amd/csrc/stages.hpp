@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(256) k_donor(Geo g, const T* __restrict__ phi,
     out[c.q] = donor_cell(g, c, phi, u, v, w, gm);
 }
 
-// Donor-cell pass over many problems and tracers (one launch): entry e owns
-// the global cells [begin, begin + tracers * cells).
+// One (problem, tracer set) of a batched copy: entry e owns the global cells
+// [begin, begin + tracers * cells).
 template <class T>
 struct DonorEntry {
     Geo geo;
@@ -121,30 +121,6 @@ struct DonorEntry {
     long long begin, cells, stride;
     int tracers;
 };
-
-template <class T>
-__global__ void __launch_bounds__(256) k_donor_batched(const DonorEntry<T>* __restrict__ tab, int n_entries,
-                                                       long long total)
-{
-    const long long step = (long long)gridDim.x * blockDim.x;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += step) {
-        int lo = 0, hi = n_entries - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].begin <= idx) lo = mid; else hi = mid - 1;
-        }
-        const DonorEntry<T>& e = tab[lo];
-        const long long r = idx - e.begin;
-        const long long tr = r / e.cells;
-        Cell c;
-        c.q = r - tr * e.cells;
-        c.k = (int)(c.q / e.geo.sz);
-        c.j = (int)((c.q - (long long)c.k * e.geo.sz) / e.geo.sy);
-        c.i = (int)(c.q - (long long)c.k * e.geo.sz - (long long)c.j * e.geo.sy);
-        const long long off = tr * e.stride;
-        e.out[off + c.q] = donor_cell(e.geo, c, e.phi + off, e.u, e.v, e.w, e.g);
-    }
-}
 
 // Antidiffusive pseudo-velocities at the three own faces of every cell.
 template <class T>

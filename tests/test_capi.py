@@ -106,3 +106,34 @@ def test_binding_refuses_host_tensors():
     x = torch.ones(2, 3, 4, dtype=torch.float64)
     with pytest.raises(ValueError):
         mp.step(x, x, x, x, x)
+
+
+def _items(mp, shapes, ptr=256):
+    """A batch item array with fake (aligned, never dereferenced) pointers."""
+    arr = (mp.BatchItem * len(shapes))()
+    for i, (nx, ny, nz, nt) in enumerate(shapes):
+        arr[i].nx, arr[i].ny, arr[i].nz, arr[i].ntracers = nx, ny, nz, nt
+        arr[i].cx = arr[i].cy = arr[i].g = arr[i].psi = ptr
+        arr[i].cz = None
+    return arr
+
+
+def _batch_ws(mp, shapes, iters=2, ptr=256):
+    p = mp.problem_for((1, 1, 1), iters=iters, dtype="f32")
+    arr = _items(mp, shapes, ptr)
+    return mp.lib().mpdata_batch_workspace_bytes(ctypes.byref(p), len(shapes), ctypes.cast(arr, ctypes.c_void_p))
+
+
+def test_batched_workspace_and_validation():
+    mp = _mp()
+    small = _batch_ws(mp, [(64, 32, 20, 1)])
+    assert small > 0
+    assert _batch_ws(mp, [(64, 32, 20, 1), (128, 64, 40, 3)]) > small
+    assert _batch_ws(mp, [(64, 32, 20, 0)]) == 0                       # no tracers
+    assert b"ntracers" in mp.lib().mpdata_last_error()
+    assert _batch_ws(mp, [(0, 32, 20, 1)]) == 0                        # empty grid
+    assert _batch_ws(mp, [(64, 32, 70000, 1)]) == 0                    # nz beyond the grid limit
+    assert _batch_ws(mp, [(64, 32, 20, 1)], ptr=258) == 0              # misaligned field
+    # 2 x 2^30 donor-pass blocks (64 x 4 columns x 16 levels each) exceed one launch
+    assert _batch_ws(mp, [(64, 4, 16, 1 << 30), (64, 4, 16, 1 << 30)]) == 0
+    assert b"blocks" in mp.lib().mpdata_last_error()
