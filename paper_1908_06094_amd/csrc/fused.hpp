@@ -10,18 +10,24 @@
 // applies to the upwind stages (Section 6.1, Table 2, Listing 9).
 //
 // Mapping onto gfx950:
-//   * a workgroup is 12 waves of 64 lanes; lane = x, wave = y.  It owns a
-//     60 x 8 interior tile plus a halo of 2 and marches up the k axis, so
-//     each stage is computed once per column and plane (no halo recompute
-//     along k).  Its LDS (114 KB in FP64) allows one workgroup per CU;
-//     12 waves leave each wave 168 VGPRs, enough to keep a column's plane
-//     history in registers without spilling;
-//   * persistent launch: one workgroup per CU, each marching an equal share
-//     of the (tile, plane) space, ranges grouped by XCD;
+//   * a workgroup is 12 waves (768 threads); lane = x, row = y.  In FP64 a
+//     tile row is one wave of 64 lanes (64 x 12 tile, 60 x 8 interior); in
+//     FP32 it is half a wave (32 x 24 tile, 28 x 20 interior).  The tile
+//     carries a halo of 2 and marches up the k axis, so each stage is
+//     computed once per column and plane (no halo recompute along k);
+//   * LDS holds one plane slot per exchanged quantity (114 KB in FP64: one
+//     workgroup per CU, 3 waves per SIMD, up to 168 VGPRs; 57 KB in FP32:
+//     two workgroups per CU, 6 waves per SIMD, up to 80 VGPRs);
+//   * persistent launch: the (tile, plane) space is cut into equal
+//     contiguous ranges, one per workgroup, grouped by XCD;
 //   * x neighbours come from DPP lane shifts (wave_shl / wave_shr), y
-//     neighbours from one LDS plane slot per exchanged quantity, k neighbours
-//     from the column's own register history;
-//   * coalesced, i-fastest HBM rows of 64 elements per wave.
+//     neighbours from the LDS slots, k neighbours from the column's own
+//     register history;
+//   * the next plane is prefetched one march step ahead with every load
+//     unconditional, and a step's results are stored at the start of the
+//     following step, before its prefetch, so that waiting for a prefetch
+//     (vmcnt counts loads and stores in order) never waits for a store;
+//   * coalesced, i-fastest HBM rows (512 B in FP64, 128 B in FP32).
 //
 // Arithmetic differs from the scheme's literal order in one place: the
 // antidiffusive velocity (|U| - U^2/Gf) A - (U/Gf)(Vb_1 B_1 + Vb_2 B_2),
@@ -55,6 +61,10 @@ struct Tile {
     static constexpr int rows = kThreads / lanes;
     static constexpr int tile_x = lanes - 2 * kHalo;   // interior columns
     static constexpr int tile_y = rows - 2 * kHalo;    // interior rows
+    // workgroups per CU: the FP32 tile's LDS (57 KB) and registers (<= 80)
+    // let two share a CU (6 waves per SIMD); the FP64 tile needs 114 KB
+    static constexpr int wgs_per_cu = sizeof(T) == 4 ? 2 : 1;
+    static constexpr int waves_per_simd = wgs_per_cu * kThreads / 256;
     static_assert((1 << shift) == lanes && lanes >= 16 && lanes <= 64, "a tile row is 16, 32 or 64 lanes");
 };
 
@@ -431,7 +441,7 @@ __device__ __forceinline__ int xcd_grouped_id()
 // workgroup, so every workgroup marches the same number of planes (a range
 // may span a tile boundary).
 template <class T, bool LIMIT, bool WRITE_VEL>
-__global__ void __launch_bounds__(kThreads) k_pass(Geo geo, PassArgs<T> a)
+__global__ void __launch_bounds__(kThreads, Tile<T>::waves_per_simd) k_pass(Geo geo, PassArgs<T> a)
 {
     __shared__ Slots<T> S;
     const int nwg = gridDim.x;

@@ -288,7 +288,8 @@ int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hi
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
     Timed tm(MPDATA_KERNEL_PASS, st);
-    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL><<<pass_grid(total), mpdata::fused::kThreads, 0, st>>>(g, a);
+    const int grid = pass_grid(total) * mpdata::fused::Tile<T>::wgs_per_cu;
+    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
     return launch_status("fused corrective pass");
 }
 
