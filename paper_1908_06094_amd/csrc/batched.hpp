@@ -43,6 +43,7 @@ struct Layout {
     int n, iters;
     std::vector<size_t> item_off;   // byte offset of item i's fields
     std::vector<long long> cells;
+    std::vector<long long> vcells;  // elements of one tracer's velocity field (tile layout)
     size_t table_bytes;
     size_t total;
     int fields_per_tracer;
@@ -64,10 +65,15 @@ inline Layout layout(const mpdata_problem* c, int n, const mpdata_batch_item* it
     L.table_bytes = align256((size_t)tables_count(c->iters) * n * entry);
     size_t off = L.table_bytes;
     for (int i = 0; i < n; ++i) {
-        const long long cells = (long long)items[i].nx * items[i].ny * items[i].nz;
+        const mpdata_batch_item& it = items[i];
+        const long long cells = (long long)it.nx * it.ny * it.nz;
+        const long long vcells = L.elem == 8 ? mpdata::fused::vel_elems<double>(it.nx, it.ny, it.nz)
+                                             : mpdata::fused::vel_elems<float>(it.nx, it.ny, it.nz);
         L.cells.push_back(cells);
+        L.vcells.push_back(vcells);
         L.item_off.push_back(off);
-        off += align256((size_t)cells * items[i].ntracers * L.elem) * L.fields_per_tracer;
+        off += align256((size_t)cells * it.ntracers * L.elem) * 3;
+        if (L.fields_per_tracer > 3) off += align256((size_t)vcells * it.ntracers * L.elem) * 6;
     }
     L.total = off;
     return L;
@@ -85,7 +91,11 @@ ItemPtrs<T> item_ptrs(const Layout& L, char* ws, const mpdata_batch_item& it, in
     ItemPtrs<T> p;
     p.user = (T*)it.psi;
     const size_t fb = align256((size_t)L.cells[i] * it.ntracers * L.elem);
-    for (int f = 0; f < 9; ++f) p.f[f] = f < L.fields_per_tracer ? (T*)(ws + L.item_off[i] + fb * f) : nullptr;
+    const size_t vb = align256((size_t)L.vcells[i] * it.ntracers * L.elem);
+    for (int f = 0; f < 9; ++f) {
+        const size_t at = f < 3 ? fb * f : fb * 3 + vb * (f - 3);
+        p.f[f] = f < L.fields_per_tracer ? (T*)(ws + L.item_off[i] + at) : nullptr;
+    }
     return p;
 }
 
@@ -172,8 +182,10 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
                 a.tiles_y = (it.ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y;
                 e.begin = pbeg;
                 e.tracer_stride = cells;
+                e.vel_stride = L.vcells[i];
                 e.tracers = it.ntracers;
                 e.vel_per_tracer = m > 2;
+                a.vel_tiled = m > 2 && mpdata::fused::Tile<T>::tiled_velocities;
                 tb.pass[par][m - 2].push_back(e);
             }
         }

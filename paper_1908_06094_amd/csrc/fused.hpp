@@ -65,6 +65,10 @@ struct Tile {
     // let two share a CU (6 waves per SIMD); the FP64 tile needs 114 KB
     static constexpr int wgs_per_cu = sizeof(T) == 4 ? 2 : 1;
     static constexpr int waves_per_simd = wgs_per_cu * kThreads / 256;
+    // velocities handed between passes in the tile layout (FP32: its 112-byte
+    // tile rows make the (nz, ny, nx) stores mostly partial cache lines; in
+    // FP64 the 480-byte rows are not, and the tile layout measured slower)
+    static constexpr bool tiled_velocities = sizeof(T) == 4;
     static_assert((1 << shift) == lanes && lanes >= 16 && lanes <= 64, "a tile row is 16, 32 or 64 lanes");
 };
 
@@ -167,12 +171,35 @@ struct PassArgs {
     const T* w;      // may be NULL: all vertical velocities 0
     const T* g;
     T* out;          // psi^(m)
-    T* ul;           // limited velocities (written when another pass follows)
-    T* vl;
+    T* ul;           // limited velocities (written when another pass follows),
+    T* vl;           // in the tile layout
     T* wl;
     double eps;
     int tiles_x, tiles_y;
+    int vel_tiled;   // u, v, w are in the tile layout (passes >= 3), else (nz, ny, nx)
 };
+
+// Tile layout of the limited velocities that one pass hands to the next
+// (where Tile<T>::tiled_velocities; otherwise they are (nz, ny, nx) fields):
+// for plane k, tile (tx, ty) (number ty * tiles_x + tx), interior row r and
+// column c, element (k * tiles + tile) * tile_x * tile_y + r * tile_x + c.
+// A tile writes its whole block of a plane in one march step, so its
+// velocity stores fill cache lines instead of ending mid line at the tile's
+// x edges.
+template <class T>
+__host__ __device__ inline long long tiled_plane(int tiles_x, int tiles_y)
+{
+    return (long long)tiles_x * tiles_y * Tile<T>::tile_x * Tile<T>::tile_y;
+}
+// Elements of one inter-pass velocity field for an nx x ny x nz grid.
+template <class T>
+__host__ __device__ inline long long vel_elems(int nx, int ny, int nz)
+{
+    if (!Tile<T>::tiled_velocities) return (long long)nx * ny * nz;
+    const int tiles_x = (nx + Tile<T>::tile_x - 1) / Tile<T>::tile_x;
+    const int tiles_y = (ny + Tile<T>::tile_y - 1) / Tile<T>::tile_y;
+    return tiled_plane<T>(tiles_x, tiles_y) * nz;
+}
 
 // Index along one axis for a virtual coordinate x (possibly outside [0, n)):
 // periodic wraps, closed clamps.
@@ -239,21 +266,26 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         const long long col = (long long)cj * geo.sy + ci;
         const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
+        // this lane's cell in the tile layout (a writer's cell lies in its own tile)
+        const int ttx = ci / kTileX, tty = cj / kTileY;
+        const long long tcol = (long long)(tty * a.tiles_x + ttx) * (kTileX * kTileY) +
+                               (cj - tty * kTileY) * kTileX + (ci - ttx * kTileX);
+        const long long tplane = tiled_plane<T>(a.tiles_x, a.tiles_y);
 
         // plane loader: cell quantities through the halo rule.  Every load is
         // issued unconditionally and the wall masks are applied where the
         // plane is consumed (one march step later), so nothing waits for a
         // prefetch on the step that issues it.
-        const bool has_w = a.w != nullptr;
-        const T* wsrc = has_w ? a.w : a.g;
+        const bool has_w = a.w != nullptr;     // without w, g is loaded in its place and masked
         auto load = [&](int k, Raw<T>& B) __attribute__((always_inline)) {
             const int ck = map_index(k, geo.nz, geo.closed_z);
             const long long q = (long long)ck * geo.sz + col;
+            const long long qv = Tile<T>::tiled_velocities && a.vel_tiled ? (long long)ck * tplane + tcol : q;
             B.phi = a.phi[q];
             if (LIMIT) B.psin = a.psin[q];
-            B.u = a.u[q];
-            B.v = a.v[q];
-            B.w = wsrc[q];
+            B.u = a.u[qv];
+            B.v = a.v[qv];
+            B.w = *(has_w ? a.w + qv : a.g + q);
             B.g = a.g[q];
         };
 
@@ -273,13 +305,16 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         auto flush = [&](const int t) __attribute__((always_inline)) {
             const int ko = t - 2;
             const long long q0 = (long long)ko * geo.sz + col;
+            const long long v0 = (long long)ko * tplane + tcol;
+            const long long w0 = Tile<T>::tiled_velocities ? v0 : q0;
+            const long long wstep = Tile<T>::tiled_velocities ? tplane : geo.sz;
             if (writer && ko >= kb && ko < ke) {
                 a.out[q0] = st_upd;
-                if (WRITE_VEL) a.wl[q0] = st_ulz;   // face (k-1)+1/2
+                if (WRITE_VEL) a.wl[w0] = st_ulz;     // face (k-1)+1/2
             }
             if (WRITE_VEL && writer && ko + 1 >= kb && ko + 1 < ke) {
-                a.ul[q0 + geo.sz] = st_ulx;          // plane k
-                a.vl[q0 + geo.sz] = st_uly;
+                a.ul[w0 + wstep] = st_ulx;             // plane k
+                a.vl[w0 + wstep] = st_uly;
             }
         };
 
@@ -471,6 +506,7 @@ struct BatchEntry {
     PassArgs<T> args;        // tracer 0's fields; tracer t adds t * tracer_stride
     long long begin;         // first work unit
     long long tracer_stride; // elements between consecutive tracers' fields
+    long long vel_stride;    // the same for the (tile-layout) velocity fields
     int tracers;
     int vel_per_tracer;      // previous velocities are per tracer (passes >= 3)
 };
@@ -508,15 +544,16 @@ __global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const
         a.phi += off;
         a.psin += off;
         a.out += off;
+        const long long voff = (long long)tracer * e.vel_stride;
         if (e.vel_per_tracer) {
-            a.u += off;
-            a.v += off;
-            if (a.w) a.w += off;
+            a.u += voff;
+            a.v += voff;
+            if (a.w) a.w += voff;
         }
         if (WRITE_VEL) {
-            a.ul += off;
-            a.vl += off;
-            a.wl += off;
+            a.ul += voff;
+            a.vl += voff;
+            a.wl += voff;
         }
         pass_segment<T, LIMIT, WRITE_VEL>(e.geo, a, S, tile, kb, ke);
     }

@@ -76,10 +76,18 @@ int validate(const mpdata_problem* p)
 size_t elem_size(const mpdata_problem* p) { return p->dtype == MPDATA_F64 ? 8 : 4; }
 long long cells(const mpdata_problem* p) { return (long long)p->nx * p->ny * p->nz; }
 
-// Every workspace field starts on a 256-byte boundary.
+// Elements of an inter-pass velocity field of the fused path.
+long long tiled_cells(const mpdata_problem* p)
+{
+    if (p->dtype == MPDATA_F64) return mpdata::fused::vel_elems<double>(p->nx, p->ny, p->nz);
+    return mpdata::fused::vel_elems<float>(p->nx, p->ny, p->nz);
+}
+
+// Every workspace field starts on a 256-byte boundary and can hold a field
+// in either layout.
 size_t field_bytes(const mpdata_problem* p)
 {
-    size_t b = (size_t)cells(p) * elem_size(p);
+    size_t b = (size_t)std::max(cells(p), tiled_cells(p)) * elem_size(p);
     return (b + 255) & ~(size_t)255;
 }
 
@@ -318,6 +326,7 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     a.u = cx;
     a.v = cy;
     a.w = cz;
+    a.vel_tiled = 0;
     const T* phi = b.phi[0];
     int vsel = 0;
     for (int m = 2; m <= p->iters; ++m) {
@@ -337,6 +346,7 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
         a.u = a.ul;
         a.v = a.vl;
         a.w = a.wl;
+        a.vel_tiled = mpdata::fused::Tile<T>::tiled_velocities;
         phi = nxt;
         vsel ^= 1;
     }
@@ -349,9 +359,12 @@ bool use_stage_kernels()
     return e && strcmp(e, "stages") == 0;
 }
 
+// ws_bytes: the size of the region at ws (checked against what the step carves)
 int dispatch_step(const mpdata_problem* p, const void* psin, void* psout, const void* cx, const void* cy,
-                  const void* cz, const void* gm, void* ws, hipStream_t st)
+                  const void* cz, const void* gm, void* ws, size_t ws_bytes, hipStream_t st)
 {
+    if (ws_bytes < step_bytes(p))
+        return fail(MPDATA_EINVAL, "internal: step workspace of %zu bytes is below %zu", ws_bytes, step_bytes(p));
     const bool stages = use_stage_kernels();
     if (p->dtype == MPDATA_F64) {
         auto f = stages ? step_stages<double> : step_fused<double>;
@@ -443,7 +456,7 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
 {
     AdjLayout L;
     L.n = cells(p);
-    L.fb = ((size_t)L.n * sizeof(double) + 255) & ~(size_t)255;
+    L.fb = field_bytes(p);   // every field, the forward step's included, fits either layout
     L.K = K;
     L.segs = nsteps > 0 ? (nsteps + K - 1) / K : 1;
     L.M = p->iters;
@@ -533,7 +546,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (int s = 0; s < nsteps; ++s) {
         const bool store = (s + 1) % K == 0 && (s + 1) / K < L.segs;
         double* dst = store ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
-        if (int rc = dispatch_step(p, cur, dst, cx, cy, cz, gm, step_ws, st)) return rc;
+        if (int rc = dispatch_step(p, cur, dst, cx, cy, cz, gm, step_ws, kStepFields * L.fb, st)) return rc;
         cur = dst;
     }
     if (psiT && cur != psiT) copy(psiT, cur);
@@ -547,7 +560,9 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
         // states psi^{s0} .. psi^{s1-1} of the segment
         copy(seg[0], ckpt[sg]);
         for (int s = s0 + 1; s < s1; ++s)
-            if (int rc = dispatch_step(p, seg[s - 1 - s0], seg[s - s0], cx, cy, cz, gm, step_ws, st)) return rc;
+            if (int rc = dispatch_step(p, seg[s - 1 - s0], seg[s - s0], cx, cy, cz, gm, step_ws, kStepFields * L.fb,
+                                       st))
+                return rc;
         for (int s = s1 - 1; s >= s0; --s) {
             const double* psin = seg[s - s0];
             // the step's intermediates, stage by stage
@@ -961,7 +976,7 @@ int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out, cons
     if (!aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < step_bytes(p))
         return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the step needs", ws_bytes, step_bytes(p));
-    return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, (hipStream_t)stream);
+    return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* cx, const void* cy, const void* cz,
@@ -985,7 +1000,7 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* c
     void* cur = psi;
     for (int s = 0; s < nsteps; ++s) {
         void* nxt = (cur == psi) ? alt : psi;
-        if (int rc = dispatch_step(p, cur, nxt, cx, cy, cz, g, ws, st)) return rc;
+        if (int rc = dispatch_step(p, cur, nxt, cx, cy, cz, g, ws, step_bytes(p), st)) return rc;
         cur = nxt;
     }
     if (cur != psi) {
