@@ -171,53 +171,80 @@ __device__ __forceinline__ void cross7(const Geo& g, int i, int j, int k, long l
     idx[6] = at(g, i, j, k + 1);
 }
 
+// The halo rule applied to each coordinate (each within one cell of the
+// domain), without dividing a linear index back into coordinates.
+struct Pt {
+    int i, j, k;
+    long long q;
+};
+__device__ __forceinline__ Pt mapped(const Geo& g, int i, int j, int k)
+{
+    Pt p;
+    p.i = nbr(i, g.nx, g.closed_x);
+    p.j = nbr(j, g.ny, g.closed_y);
+    p.k = nbr(k, g.nz, g.closed_z);
+    p.q = (long long)p.k * g.sz + (long long)p.j * g.sy + p.i;
+    return p;
+}
+
+// Entry d (0 self, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z) of cell (i, j, k)'s cross.
+// Branch-free: d differs from lane to lane.
+__device__ __forceinline__ long long cross_entry(const Geo& g, int i, int j, int k, int d)
+{
+    const int di = d == 1 ? -1 : (d == 2 ? 1 : 0);
+    const int dj = d == 3 ? -1 : (d == 4 ? 1 : 0);
+    const int dk = d == 5 ? -1 : (d == 6 ? 1 : 0);
+    return at(g, i + di, j + dj, k + dk);
+}
+
+// The bounds and, in code[2q] / code[2q+1], the first maximal / minimal
+// entry e of the 14 (psi^n at the cross's 7 cells, then the iterate), the
+// entry through which the adjoint of mx / mn flows.
 __global__ void __launch_bounds__(256) k_bounds(Geo g, const double* __restrict__ psin, const double* __restrict__ phi,
-                                                double* __restrict__ mx, double* __restrict__ mn)
+                                                double* __restrict__ mx, double* __restrict__ mn,
+                                                unsigned char* __restrict__ code)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
     long long idx[7];
     cross7(g, c.i, c.j, c.k, idx);
     double hi = psin[idx[0]], lo = hi;
-    for (int f = 0; f < 2; ++f)
-        for (int o = 0; o < 7; ++o) {
-            const double v = (f ? phi : psin)[idx[o]];
-            hi = max2(hi, v);
-            lo = min2(lo, v);
-        }
+    int am = 0, an = 0;
+    for (int e = 1; e < 14; ++e) {
+        const double v = (e < 7 ? psin : phi)[idx[e % 7]];
+        if (v > hi) { hi = v; am = e; }
+        if (v < lo) { lo = v; an = e; }
+    }
     mx[c.q] = hi;
     mn[c.q] = lo;
+    code[2 * c.q] = (unsigned char)am;
+    code[2 * c.q + 1] = (unsigned char)an;
 }
 
 // (lmx, lmn) -> lpsin (+=), lphi (+=): each cell x collects from the distinct
-// cells whose cross contains it, where x is the first maximal / minimal entry.
-__global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const double* __restrict__ psin,
-                                                    const double* __restrict__ phi, const double* __restrict__ lmx,
-                                                    const double* __restrict__ lmn, double* __restrict__ lpsin,
-                                                    double* __restrict__ lphi)
+// cells whose cross contains it, where x is the recorded first maximal /
+// minimal entry.
+__global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* __restrict__ code,
+                                                    const double* __restrict__ lmx, const double* __restrict__ lmn,
+                                                    double* __restrict__ lpsin, double* __restrict__ lphi)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
-    long long cand[7];
-    cross7(g, c.i, c.j, c.k, cand);   // the cells whose cross contains c (the cross is symmetric)
+    // the cells whose cross contains c (the cross is symmetric)
+    const Pt cand[7] = {mapped(g, c.i, c.j, c.k),     mapped(g, c.i - 1, c.j, c.k), mapped(g, c.i + 1, c.j, c.k),
+                        mapped(g, c.i, c.j - 1, c.k), mapped(g, c.i, c.j + 1, c.k), mapped(g, c.i, c.j, c.k - 1),
+                        mapped(g, c.i, c.j, c.k + 1)};
     double gp = 0.0, gf = 0.0;
+#pragma unroll
     for (int m = 0; m < 7; ++m) {
         bool dup = false;
-        for (int m2 = 0; m2 < m; ++m2) dup = dup || cand[m2] == cand[m];
+#pragma unroll
+        for (int m2 = 0; m2 < m; ++m2) dup = dup || cand[m2].q == cand[m].q;
         if (dup) continue;
-        const long long qc = cand[m];
-        const int kk = (int)(qc / g.sz), jj = (int)((qc % g.sz) / g.sy), ii = (int)(qc % g.sy);
-        long long idx[7];
-        cross7(g, ii, jj, kk, idx);
-        int am = 0, an = 0;
-        double vm = psin[idx[0]], vn = vm;
-        for (int e = 1; e < 14; ++e) {
-            const double val = (e < 7 ? psin : phi)[idx[e % 7]];
-            if (val > vm) { vm = val; am = e; }
-            if (val < vn) { vn = val; an = e; }
-        }
-        if (idx[am % 7] == c.q) (am < 7 ? gp : gf) += lmx[qc];
-        if (idx[an % 7] == c.q) (an < 7 ? gp : gf) += lmn[qc];
+        const Pt& y = cand[m];
+        const int am = code[2 * y.q], an = code[2 * y.q + 1];
+        if (cross_entry(g, y.i, y.j, y.k, am % 7) == c.q) (am < 7 ? gp : gf) += lmx[y.q];
+        if (cross_entry(g, y.i, y.j, y.k, an % 7) == c.q) (an < 7 ? gp : gf) += lmn[y.q];
     }
     lpsin[c.q] += gp;
     lphi[c.q] += gf;
@@ -467,8 +494,10 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
         return;
     }
 
+    // Every loop below is unrolled so that the small tables and the seen
+    // lists live in registers (indexed by compile-time constants).
     double acc = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         int tr[2];
         {
@@ -498,16 +527,19 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                     }
         }
         long long seen[10];
-        int nseen = 0;
+#pragma unroll
         for (int m = 0; m < 10; ++m) {
-            const long long y = at(g, c.i - off[m][0], c.j - off[m][1], c.k - off[m][2]);
+            const Pt yp = mapped(g, c.i - off[m][0], c.j - off[m][1], c.k - off[m][2]);
+            const long long y = yp.q;
+            seen[m] = y;
             bool dup = false;
-            for (int s2 = 0; s2 < nseen; ++s2) dup = dup || seen[s2] == y;
+#pragma unroll
+            for (int s2 = 0; s2 < m; ++s2) dup = dup || seen[s2] == y;
             if (dup) continue;
-            seen[nseen++] = y;
-            const int yk = (int)(y / g.sz), yj = (int)((y % g.sz) / g.sy), yi = (int)(y % g.sy);
+            const int yk = yp.k, yj = yp.j, yi = yp.i;
             if (face_idx(g, a, yi, yj, yk) < 0) continue;   // wall: U~ is the constant 0
             const double* s = slots + (long long)a * kSlots * field + y;
+#pragma unroll
             for (int e = 0; e < 10; ++e) {
                 if (at(g, yi + off[e][0], yj + off[e][1], yk + off[e][2]) == x) acc += s[slot_of[e] * field];
             }
@@ -518,12 +550,13 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
     // velocities of x's own faces: face (t, x) is read as the own velocity of
     // face (t, x) and in the transverse averages of faces (a != t, y) at
     // V_t(y), V_t(y+a), V_t(y-t), V_t(y+a-t)
-#pragma unroll 1
+#pragma unroll
     for (int t = 0; t < 3; ++t) {
         if (!lvel[t]) continue;
         const long long fx = face_idx(g, t, c.i, c.j, c.k);
         if (fx < 0) continue;
         double accv = slots[((long long)t * kSlots + 8) * field + x];
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (a == t) continue;
             // position of t among a's transverse axes in increasing order
@@ -533,8 +566,8 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
             o4[2][t] = -1;
             o4[3][a] = 1;
             o4[3][t] = -1;
-            long long seen[4];
-            int nseen = 0;
+            long long seen[4] = {-1, -1, -1, -1};
+#pragma unroll
             for (int m = 0; m < 4; ++m) {
                 int yc[3] = {c.i - o4[m][0], c.j - o4[m][1], c.k - o4[m][2]};
                 // the face coordinate along t stays a face index: map the
@@ -549,12 +582,14 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                     yt -= nt;
                 }
                 yc[t] = yt;
-                const long long y = at(g, yc[0], yc[1], yc[2]);
+                const Pt yp = mapped(g, yc[0], yc[1], yc[2]);
+                const long long y = yp.q;
+                seen[m] = y;
                 bool dup = false;
-                for (int s2 = 0; s2 < nseen; ++s2) dup = dup || seen[s2] == y;
+#pragma unroll
+                for (int s2 = 0; s2 < m; ++s2) dup = dup || seen[s2] == y;
                 if (dup) continue;
-                seen[nseen++] = y;
-                const int yk = (int)(y / g.sz), yj = (int)((y % g.sz) / g.sy), yi = (int)(y % g.sy);
+                const int yk = yp.k, yj = yp.j, yi = yp.i;
                 if (face_idx(g, a, yi, yj, yk) < 0) continue;
                 int ry[3] = {yi, yj, yk};
                 ry[a] += 1;

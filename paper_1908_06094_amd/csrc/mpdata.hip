@@ -461,10 +461,10 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     L.segs = nsteps > 0 ? (nsteps + K - 1) / K : 1;
     L.M = p->iters;
     // checkpoints + segment states + per pass (phi, U~ x3, V x3, beta x2, mx,
-    // mn) + 18 adjoint fields (cur, prev, psin, V x3, Vprev x3, U~ x3, beta x2,
-    // lin, lout, lmx, lmn) + antidiffusive slots (27) + a forward step's
-    // workspace + a zero field and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)11 * L.M + 18 + 27 + kStepFields + 2;
+    // mn, extremal-entry codes) + 18 adjoint fields (cur, prev, psin, V x3,
+    // Vprev x3, U~ x3, beta x2, lin, lout, lmx, lmn) + antidiffusive slots (27)
+    // + a forward step's workspace + a zero field and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)12 * L.M + 18 + 27 + kStepFields + 2;
     return L;
 }
 
@@ -485,12 +485,14 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     const int M = L.M;
     std::vector<double*> phis(M + 1, nullptr), ut(3 * (M + 1), nullptr), vl(3 * (M + 1), nullptr),
         bu(M + 1, nullptr), bd(M + 1, nullptr), mx(M + 1, nullptr), mn(M + 1, nullptr);
+    std::vector<unsigned char*> code(M + 1, nullptr);   // 2 bytes per cell in a field of 8
     for (int m = 1; m <= M; ++m) {
         phis[m] = field();
         bu[m] = field();
         bd[m] = field();
         mx[m] = field();
         mn[m] = field();
+        code[m] = (unsigned char*)field();
         for (int a = 0; a < 3; ++a) {
             ut[3 * m + a] = field();
             vl[3 * m + a] = field();
@@ -576,7 +578,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                                                           U3[1], U3[2]);
                 for (int a = 0; a < 3; ++a) copy(V3[a], U3[a]);
                 if (p->limiter) {
-                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, phis[m - 1], mx[m], mn[m]);
+                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, phis[m - 1], mx[m], mn[m], code[m]);
                     S::k_beta<double><<<grd, blk, 0, st>>>(g, eps, psin, phis[m - 1], U3[0], U3[1], U3[2], gm, bu[m],
                                                           bd[m]);
                     S::k_limit<double><<<grd, blk, 0, st>>>(g, V3[0], V3[1], V3[2], bu[m], bd[m]);
@@ -605,7 +607,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                                                         lin, lout, lmx, lmn, lprev);
                     A::k_adj_beta2<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, lprev, lut[0], lut[1],
                                                         lut[2]);
-                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, psin, ph, lmx, lmn, lpsin, lprev);
+                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, code[m], lmx, lmn, lpsin, lprev);
                 } else {
                     for (int a = 0; a < 3; ++a) copy(lut[a], lv[a]);
                 }

@@ -208,7 +208,8 @@ def test_config3_full_size_one_step():
 TOL32 = 3e-5
 
 
-@pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6]])
+@pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6], CASES[8],
+                                                CASES[10]])
 def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
     torch = _torch()
     mp = _mp()
