@@ -81,10 +81,11 @@ def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
         kernel = "fused corrective pass (k_pass)"
         traffic = traffic_record(profsum.kernel_source_sha(), dtype)
     else:
+        # no per-launch records (per-stage path, or a graph replay): one step
         bytes_per_launch = bytes_per_cell_step(elem) * w.cells
         avg_s = stage_ms * 1e-3 / max(stage_n, 1) if stage_n else ev_ms * 1e-3 / steps
         ops = model.step_ops(w.iters, w.limiter)
-        kernel = "per-stage kernels of one step"
+        kernel = "per-stage kernels of one step" if stage_n else "one whole step (HIP events around the replay)"
         traffic = None
     achieved = bytes_per_launch / avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -186,6 +187,8 @@ def main():
                     help="skip the adjoint/forward timing on the 256x128x60 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain device copy of one field (for counter calibration)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the steps as replays of one captured HIP graph (launch-bound small grids)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -221,11 +224,27 @@ def main():
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    graph = None
+    if args.graph:
+        # the K steps captured once on a side stream, then replayed
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                mp.run(psi, cx, cy, cz, g, args.steps, **kw)
+        stream.wait_stream(side)
+        graph.replay()               # one untimed replay
+        torch.cuda.synchronize()
+        log(f"[bench] captured {args.steps} steps in one graph")
     torch.cuda.synchronize()
     mp.timing_enable(True)          # HIP events around every kernel launch, on the launch stream
     t0 = time.perf_counter()
     ev0.record(stream)
-    mp.run(psi, cx, cy, cz, g, args.steps, **kw)
+    if graph is not None:
+        graph.replay()
+    else:
+        mp.run(psi, cx, cy, cz, g, args.steps, **kw)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -249,6 +268,22 @@ def main():
     if not args.no_batched:
         batched = time_batched(mp, torch, dev)
 
+    # practical HBM ceiling: a plain device copy of one field, read + write
+    csrc = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(5):
+        c0.record(stream)
+        cdst.copy_(csrc)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms.append(c0.elapsed_time(c1))
+    copy_gbs = 2 * w.cells * elem / (float(np.median(copy_ms)) * 1e-3) / 1e9
+    del csrc, cdst
+
     if args.copy_calibration:
         src = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -258,6 +293,7 @@ def main():
         log(f"[bench] copy calibration: 3 copies of {src.numel() * elem} bytes")
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         import oracle
 
@@ -279,6 +315,18 @@ def main():
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{n} full step(s) of {w.name} (FP64, plain C, OpenMP over levels), {cpu_s:.1f} s"}
         log(f"[bench] cpu oracle: {n} steps in {cpu_s:.1f} s")
+        # the same n steps on the GPU from the same start: errors against the oracle
+        x = torch.from_numpy(w.psi).to(dev, tdt)
+        m0 = mp.mass(x, g, bc=w.bc)
+        mp.run(x, cx, cy, cz, g, n, **kw)
+        m1 = mp.mass(x, g, bc=w.bc)
+        got = x.double().cpu().numpy()
+        diff = got - out
+        accuracy = {"steps": n, "max_abs_err_rel": float(np.max(np.abs(diff)) / np.max(np.abs(out))),
+                    "rms_err_rel": float(np.sqrt(np.mean(diff * diff)) / np.sqrt(np.mean(out * out))),
+                    "mass_drift_rel": float(abs(m1 - m0) / m0), "min_psi": float(got.min()),
+                    "against": "the CPU oracle (FP64) from the same start"}
+        log(f"[bench] accuracy after {n} steps: {accuracy}")
 
     line = {
         "metric": METRIC,
@@ -303,6 +351,11 @@ def main():
                  "pass_launches": pass_n, "pass_ms_avg": round(pass_ms / max(pass_n, 1), 4),
                  "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "hbm_copy": {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                     "pass_frac_of_copy": round(roof["achieved"] / copy_gbs, 4),
+                     "what": "torch device copy of one field (read + write), median of 5"},
+        "graph": bool(graph is not None),
         "adjoint": adjoint,
         "batched": batched,
     }

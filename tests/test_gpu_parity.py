@@ -246,3 +246,38 @@ def test_fp32_config3_full_size():
     assert _rel(got, want) <= TOL32
     assert got.min() >= 0.0
     assert abs(mp.mass(t, args[3]) - m0) <= 1e-6 * m0
+
+
+def test_run_captured_in_a_graph_matches_eager():
+    """mpdata_run enqueued under torch's HIP graph capture (kernels and a
+    device copy, no memset nodes): every replay, with eager work and
+    synchronisations in between, equals the eager result."""
+    torch = _torch()
+    mp = _mp()
+    shape, bc = (6, 21, 70), (P, C, C)
+    _say(f"[graph] shape={shape} bc={bc} 3 steps, 3 passes, limiter")
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=77, courant=0.8)
+    dv = [_dev(a) for a in (cx, cy, cz, g)]
+    start = _dev(psi)
+    p = mp.problem_for(shape, bc, 3, True, "f64")
+    ws = torch.empty(mp.workspace_bytes(p, mp.MPDATA_OP_RUN), dtype=torch.uint8, device="cuda")
+    eager = start.clone()
+    mp.run(eager, *dv, 3, iters=3, limiter=True, bc=bc, workspace=ws)
+    torch.cuda.synchronize()
+    x = start.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            mp.run(x, *dv, 3, iters=3, limiter=True, bc=bc, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        x.copy_(start)
+        junk = torch.ones(1 << 16, dtype=torch.float64, device="cuda").cumsum(0)   # eager work between
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(x, eager), rep
+        del junk
