@@ -148,6 +148,44 @@ int mpdata_run_batched(const mpdata_problem* common, int32_t nitems,
                        const mpdata_batch_item* items, int32_t nsteps, int32_t flags,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Unstructured (edge-based) donor-cell step: the paper's own MPDATA dwarf
+ * (Section 5): the upwind flux on every edge (Listings 4-5), the vertical
+ * upwind flux with the boundary factor pivbz (Listing 7: the flux through
+ * the bottom and top of a column is pivbz times the nearest interior
+ * interface flux, 0 closes the column), the flux divergence at the nodes
+ * over the dual volumes (Listing 8) and the update:
+ *   div[n][k] = (sum over n's edges of sign * flux[e][k]) / vol[n]
+ *               + (fz[n][k+1] - fz[n][k]),   out[n][k] = psi[n][k] - div / rho[n][k]
+ * with flux[e][k] = max(0, vn) psi[ip1][k] + min(0, vn) psi[ip2][k].
+ *
+ * Layout (device arrays): per-node fields (n_nodes, nz) and per-edge fields
+ * (n_edges, nz), level fastest, of the mesh's dtype.  w[n][k] (k >= 1) is
+ * the vertical Courant number at the interface between levels k-1 and k;
+ * w may be NULL (no vertical wind).  A positive vn[e][k] carries psi from
+ * ip1 to ip2.  The connectivity is read as given: every index must be in
+ * range (the library does not scan device memory; an index out of range is
+ * a memory fault).  Dual volumes and rho must be positive.  The caller owns
+ * every buffer; the calls enqueue on `stream` and allocate nothing. */
+typedef struct {
+    int32_t n_nodes, n_edges, nz;  /* >= 1, >= 0, >= 1                                 */
+    int32_t dtype;                 /* MPDATA_F64 or MPDATA_F32 (fields, dual volumes)  */
+    double pivbz;                  /* vertical boundary factor                         */
+    const int32_t* edge_nodes;     /* (n_edges, 2): ip1, ip2                           */
+    const int32_t* node_ptr;       /* (n_nodes + 1) offsets into node_edges, [0] = 0    */
+    const int32_t* node_edges;     /* node n's edges at [node_ptr[n], node_ptr[n+1])   */
+    const int8_t* node_sign;       /* +1 where the node is the edge's ip1, -1 for ip2  */
+    const void* dual_volume;       /* (n_nodes)                                        */
+} mpdata_umesh;
+
+/* One step: psi_out must not alias psi_in. */
+int mpdata_ustep(const mpdata_umesh* m, const void* psi_in, void* psi_out, const void* vn, const void* w,
+                 const void* rho, void* stream);
+/* nsteps steps in place on psi; ws: at least mpdata_uworkspace_bytes(m). */
+size_t mpdata_uworkspace_bytes(const mpdata_umesh* m);
+int mpdata_urun(const mpdata_umesh* m, int32_t nsteps, void* psi, const void* vn, const void* w,
+                const void* rho, void* ws, size_t ws_bytes, void* stream);
+
 /* Mass sum(G * psi) accumulated in FP64 (compensated) for either dtype,
  * written to *host_out.  Synchronises `stream`.  ws: at least the
  * MPDATA_OP_MASS size. */
@@ -165,8 +203,9 @@ const char* mpdata_last_error(void);
  * returns the summed elapsed milliseconds and the number of launches.  Kinds:
  *   MPDATA_KERNEL_PASS   the fused corrective-pass kernel
  *   MPDATA_KERNEL_DONOR  the donor-cell pass ahead of the fused passes
- *   MPDATA_KERNEL_STAGE  the per-stage kernels (MPDATA_KERNELS=stages) */
-enum { MPDATA_KERNEL_PASS = 0, MPDATA_KERNEL_DONOR = 1, MPDATA_KERNEL_STAGE = 2 };
+ *   MPDATA_KERNEL_STAGE  the per-stage kernels (MPDATA_KERNELS=stages)
+ *   MPDATA_KERNEL_USTEP  the unstructured step kernel */
+enum { MPDATA_KERNEL_PASS = 0, MPDATA_KERNEL_DONOR = 1, MPDATA_KERNEL_STAGE = 2, MPDATA_KERNEL_USTEP = 3 };
 int mpdata_timing_enable(int32_t on);
 int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches);
 

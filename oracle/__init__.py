@@ -6,6 +6,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 rational model (``exact.py``) are written independently of the HIP kernels.
 """
 from .ref import (  # noqa: F401
+    ustep, urun,
     RefProblem,
     adjoint,
     antidiff,

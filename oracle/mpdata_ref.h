@@ -98,6 +98,36 @@ int ref_adjoint(const ref_problem* p, int32_t nsteps, const double* psi0,
 /* Threads the oracle's parallel loops use (OpenMP). */
 int ref_num_threads(void);
 
+/* ------------------------------------------------------------------------
+ * Edge-based donor-cell step on an unstructured mesh (the paper's own MPDATA
+ * dwarf, Section 5, Listings 4-9): upwind flux on every edge (Listings 4-5),
+ * vertical upwind flux with the boundary factor pivbz (Listing 7), flux
+ * divergence at the nodes through the node-to-edge table and its signs,
+ * divided by the dual volume (Listing 8), and the solution update.
+ *
+ * Layout: per-node fields (n_nodes, nz), per-edge fields (n_edges, nz),
+ * level fastest.  edges[2e], edges[2e+1] = ip1, ip2; a positive vn[e][k]
+ * carries psi from ip1 to ip2.  node_edges[node_ptr[n] .. node_ptr[n+1]) are
+ * node n's edges with node_sign +1 where n is the edge's ip1, -1 where it is
+ * ip2.  w[n][k] (k >= 1) is the vertical Courant number at the interface
+ * between levels k-1 and k (w[n][0] is not read).
+ *
+ *   flux[e][k] = max(0, vn) psi[ip1][k] + min(0, vn) psi[ip2][k]
+ *   fz[n][k]   = max(0, w[n][k]) psi[n][k-1] + min(0, w[n][k]) psi[n][k], 1 <= k <= nz-1
+ *   fz[n][0]   = pivbz fz[n][1],  fz[n][nz] = pivbz fz[n][nz-1]   (nz = 1: no vertical flux)
+ *   div[n][k]  = (sum over n's edges, in table order, of sign * flux) / vol[n]
+ *                + (fz[n][k+1] - fz[n][k])
+ *   out[n][k]  = psi[n][k] - div[n][k] / rho[n][k]
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_nodes, n_edges, nz;
+    double pivbz;
+} ref_umesh;
+
+int ref_ustep(const ref_umesh* m, const int32_t* edges, const int32_t* node_ptr, const int32_t* node_edges,
+              const int8_t* node_sign, const double* vol, const double* psi, const double* vn,
+              const double* w, const double* rho, double* out);
+
 #ifdef __cplusplus
 }
 #endif

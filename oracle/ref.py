@@ -67,6 +67,11 @@ class RefProblem:
         return s
 
 
+class _UMesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("pivbz", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.POINTER(ctypes.c_double)
 
@@ -93,6 +98,10 @@ def _load():
         lib.ref_adjoint.restype = ctypes.c_int
         lib.ref_num_threads.argtypes = []
         lib.ref_num_threads.restype = ctypes.c_int
+        _I32 = ctypes.POINTER(ctypes.c_int32)
+        _I8 = ctypes.POINTER(ctypes.c_int8)
+        lib.ref_ustep.argtypes = [ctypes.POINTER(_UMesh), _I32, _I32, _I32, _I8] + [_P] * 6
+        lib.ref_ustep.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -196,3 +205,33 @@ def adjoint(p: RefProblem, nsteps: int, psi0, cx, cy, cz, g, seed):
     _call("ref_adjoint", ctypes.byref(p.c()), int(nsteps), _ptr(psi0), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
           _ptr(seed), *[_ptr(o) for o in out])
     return tuple(out)
+
+
+def ustep(edges, node_ptr, node_edges, node_sign, vol, psi, vn, w, rho, pivbz=0.0):
+    """Unstructured donor-cell step (see mpdata_ref.h): psi, w, rho are
+    (nodes, nz), vn is (edges, nz), edges is (edges, 2)."""
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    nn, nz = psi.shape
+    edges = np.ascontiguousarray(edges, dtype=np.int32)
+    ne = edges.shape[0]
+    node_ptr = np.ascontiguousarray(node_ptr, dtype=np.int32)
+    node_edges = np.ascontiguousarray(node_edges, dtype=np.int32)
+    node_sign = np.ascontiguousarray(node_sign, dtype=np.int8)
+    vol = np.ascontiguousarray(vol, dtype=np.float64)
+    vn = np.ascontiguousarray(vn, dtype=np.float64).reshape(ne, nz) if ne else np.zeros((1, nz))
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(nn, nz)
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(nn, nz)
+    out = np.empty((nn, nz))
+    m = _UMesh(nn, ne, nz, float(pivbz))
+    i32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _call("ref_ustep", ctypes.byref(m), i32(edges), i32(node_ptr), i32(node_edges),
+          node_sign.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _ptr(vol), _ptr(psi), _ptr(vn), _ptr(w),
+          _ptr(rho), _ptr(out))
+    return out
+
+
+def urun(nsteps, edges, node_ptr, node_edges, node_sign, vol, psi, vn, w, rho, pivbz=0.0):
+    out = np.array(psi, dtype=np.float64, copy=True)
+    for _ in range(nsteps):
+        out = ustep(edges, node_ptr, node_edges, node_sign, vol, out, vn, w, rho, pivbz)
+    return out

@@ -6,7 +6,8 @@ binding fails loudly if the built library is missing; there is no fallback.
 
 Fields are contiguous torch tensors of shape (nz, ny, nx), dtype float64 or
 float32, on a ROCm device.  Boundary conditions are per axis (x, y, z):
-"periodic" or "closed".
+"periodic" or "closed".  The unstructured (edge-based) step takes
+(nodes, levels) and (edges, levels) tensors and a DeviceMesh.
 """
 from __future__ import annotations
 
@@ -17,6 +18,7 @@ from ._lib import (  # noqa: F401
     MPDATA_KERNEL_DONOR,
     MPDATA_KERNEL_PASS,
     MPDATA_KERNEL_STAGE,
+    MPDATA_KERNEL_USTEP,
     MPDATA_OP_ADJOINT,
     MPDATA_OP_MASS,
     MPDATA_OP_RUN,
@@ -25,6 +27,10 @@ from ._lib import (  # noqa: F401
     MPDATA_BATCH_GRAPH,
     MPDATA_BATCH_TUNE,
     BatchItem,
+    DeviceMesh,
+    UMesh,
+    urun,
+    ustep,
     MpdataError,
     batch_problem,
     run_batched,

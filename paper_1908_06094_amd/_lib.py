@@ -28,9 +28,18 @@ class Problem(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps", ctypes.c_double)]
 
 
+class UMesh(ctypes.Structure):
+    """mpdata_umesh: an unstructured mesh whose tables live in device memory."""
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("pivbz", ctypes.c_double), ("edge_nodes", ctypes.c_void_p),
+                ("node_ptr", ctypes.c_void_p), ("node_edges", ctypes.c_void_p), ("node_sign", ctypes.c_void_p),
+                ("dual_volume", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _pp = ctypes.POINTER(Problem)
+_up = ctypes.POINTER(UMesh)
 
 _SIGNATURES = {
     "mpdata_workspace_bytes": ([_pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
@@ -42,13 +51,16 @@ _SIGNATURES = {
     "mpdata_batch_workspace_bytes": ([_pp, ctypes.c_int32, _vp], ctypes.c_size_t),
     "mpdata_run_batched": ([_pp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _vp],
                            ctypes.c_int),
+    "mpdata_ustep": ([_up, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "mpdata_uworkspace_bytes": ([_up], ctypes.c_size_t),
+    "mpdata_urun": ([_up, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_last_error": ([], ctypes.c_char_p),
     "mpdata_timing_enable": ([ctypes.c_int32], ctypes.c_int),
     "mpdata_timing_read": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                            ctypes.c_int),
 }
 
-MPDATA_KERNEL_PASS, MPDATA_KERNEL_DONOR, MPDATA_KERNEL_STAGE = 0, 1, 2
+MPDATA_KERNEL_PASS, MPDATA_KERNEL_DONOR, MPDATA_KERNEL_STAGE, MPDATA_KERNEL_USTEP = 0, 1, 2, 3
 
 
 def lib_path() -> str:
@@ -308,3 +320,86 @@ def run_batched(problems, nsteps, *, iters=2, limiter=True, bc=("periodic", "clo
     flags = (MPDATA_BATCH_GRAPH if graph else 0) | (MPDATA_BATCH_TUNE if tune else 0)
     _check(lib().mpdata_run_batched(ctypes.byref(p), len(problems), ctypes.cast(items, ctypes.c_void_p),
                                     int(nsteps), flags, _ptr(ws), ws.numel(), ctypes.c_void_p(st.cuda_stream)))
+
+
+# ---------------------------------------------------------------------------
+# Unstructured (edge-based) donor-cell step
+# ---------------------------------------------------------------------------
+
+class DeviceMesh:
+    """An unstructured mesh uploaded to the device: the connectivity is
+    checked on the host (every index in range, the node table consistent
+    with the edge table) before it is copied, so the kernels only ever see
+    valid indices.  Keeps the device arrays alive as long as the mesh."""
+
+    def __init__(self, edges, node_ptr, node_edges, node_sign, dual_volume, nz, *, dtype="f64", pivbz=0.0,
+                 device="cuda"):
+        import numpy as np
+        import torch
+
+        edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        node_ptr = np.ascontiguousarray(node_ptr, dtype=np.int32)
+        node_edges = np.ascontiguousarray(node_edges, dtype=np.int32)
+        node_sign = np.ascontiguousarray(node_sign, dtype=np.int8)
+        vol = np.ascontiguousarray(dual_volume, dtype=np.float64)
+        nn, ne = len(node_ptr) - 1, len(edges)
+        if nn < 1 or nz < 1 or len(vol) != nn:
+            raise ValueError("mesh sizes are inconsistent")
+        if node_ptr[0] != 0 or node_ptr[-1] != len(node_edges) or np.any(np.diff(node_ptr) < 0):
+            raise ValueError("node_ptr must start at 0, be non-decreasing and end at len(node_edges)")
+        if len(node_sign) != len(node_edges) or not np.all(np.abs(node_sign) == 1):
+            raise ValueError("node_sign must hold +1 / -1 for every node_edges entry")
+        if ne and (edges.min() < 0 or edges.max() >= nn):
+            raise ValueError("edge node index out of range")
+        if len(node_edges) and (node_edges.min() < 0 or node_edges.max() >= ne):
+            raise ValueError("node edge index out of range")
+        if not np.all(vol > 0):
+            raise ValueError("dual volumes must be positive")
+        self.dtype = torch.float64 if dtype == "f64" else torch.float32
+        dev = torch.device(device)
+        as_dev = lambda a: torch.from_numpy(a).to(dev)
+        self._keep = [as_dev(edges.reshape(-1)), as_dev(node_ptr), as_dev(node_edges if len(node_edges) else
+                      np.zeros(1, np.int32)), as_dev(node_sign if len(node_sign) else np.zeros(1, np.int8)),
+                      torch.from_numpy(vol).to(dev, self.dtype)]
+        self.c = UMesh(nn, ne, int(nz), MPDATA_F64 if dtype == "f64" else MPDATA_F32, float(pivbz),
+                       *[t.data_ptr() for t in self._keep])
+        self.n_nodes, self.n_edges, self.nz, self.device = nn, ne, int(nz), dev
+
+    @classmethod
+    def from_octa(cls, mesh, nz, **kw):
+        return cls(mesh.edges, mesh.node_ptr, mesh.node_edges, mesh.node_sign, mesh.dual_volume, nz, **kw)
+
+
+def _ufields(m, psi, vn, w, rho):
+    import torch
+
+    for t, shape, what in ((psi, (m.n_nodes, m.nz), "psi"), (vn, (m.n_edges, m.nz), "vn"),
+                           (w, (m.n_nodes, m.nz), "w"), (rho, (m.n_nodes, m.nz), "rho")):
+        if t is None and what == "w":
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != m.dtype:
+            raise ValueError(f"{what} must be a contiguous device tensor of the mesh's dtype")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {shape}")
+    return torch.cuda.current_stream(psi.device).cuda_stream
+
+
+def ustep(m, psi, vn, w, rho, out=None):
+    """One unstructured donor-cell step on the current stream; returns the new field."""
+    import torch
+
+    stream = _ufields(m, psi, vn, w, rho)
+    out = torch.empty_like(psi) if out is None else out
+    _check(lib().mpdata_ustep(ctypes.byref(m.c), _ptr(psi), _ptr(out), _ptr(vn), _ptr(w), _ptr(rho),
+                              ctypes.c_void_p(stream)))
+    return out
+
+
+def urun(m, psi, vn, w, rho, nsteps, workspace=None):
+    """nsteps unstructured steps in place on psi."""
+    stream = _ufields(m, psi, vn, w, rho)
+    nb = lib().mpdata_uworkspace_bytes(ctypes.byref(m.c))
+    ws = workspace if workspace is not None else _workspace(nb, psi.device)
+    _check(lib().mpdata_urun(ctypes.byref(m.c), int(nsteps), _ptr(psi), _ptr(vn), _ptr(w), _ptr(rho), _ptr(ws),
+                             ws.numel(), ctypes.c_void_p(stream)))
+    return psi

@@ -494,10 +494,11 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
         return;
     }
 
-    // Every loop below is unrolled so that the small tables and the seen
-    // lists live in registers (indexed by compile-time constants).
+    // The loops inside the axis loop are unrolled so that the small tables
+    // and the seen lists live in registers (indexed by compile-time
+    // constants); the axis loop itself stays a loop (its body is large).
     double acc = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int a = 0; a < 3; ++a) {
         int tr[2];
         {

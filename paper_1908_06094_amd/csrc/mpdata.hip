@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -23,6 +24,7 @@
 #include "donor.hpp"
 #include "adjoint.hpp"
 #include "batched.hpp"
+#include "unstructured.hpp"
 
 namespace {
 
@@ -138,7 +140,7 @@ int launch_status(const char* what)
 struct KernelTiming {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[3];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[4];
     std::vector<hipEvent_t> spare;
 };
 KernelTiming g_timing;
@@ -902,6 +904,79 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// Unstructured (edge-based) donor-cell step
+// ---------------------------------------------------------------------------
+
+size_t uelem(const mpdata_umesh* m) { return m->dtype == MPDATA_F64 ? 8 : 4; }
+
+int validate_umesh(const mpdata_umesh* m)
+{
+    if (!m) return fail(MPDATA_EINVAL, "mesh pointer is NULL");
+    if (m->n_nodes < 1 || m->n_edges < 0 || m->nz < 1)
+        return fail(MPDATA_EINVAL, "mesh sizes n_nodes=%d n_edges=%d nz=%d out of range", m->n_nodes, m->n_edges,
+                    m->nz);
+    if ((long long)m->n_nodes * m->nz > (1LL << 40) || (long long)m->n_edges * m->nz > (1LL << 40))
+        return fail(MPDATA_EINVAL, "mesh too large");
+    if (m->dtype != MPDATA_F64 && m->dtype != MPDATA_F32)
+        return fail(MPDATA_EINVAL, "dtype=%d is neither MPDATA_F64 nor MPDATA_F32", m->dtype);
+    if (!std::isfinite(m->pivbz)) return fail(MPDATA_EINVAL, "pivbz is not finite");
+    if (!m->node_ptr || !aligned(m->node_ptr, 4) || !m->dual_volume || !aligned(m->dual_volume, uelem(m)))
+        return fail(MPDATA_EINVAL, "node_ptr or dual_volume is NULL or misaligned");
+    if (m->n_edges > 0 && (!m->edge_nodes || !aligned(m->edge_nodes, 4) || !m->node_edges ||
+                           !aligned(m->node_edges, 4) || !m->node_sign))
+        return fail(MPDATA_EINVAL, "an edge table is NULL or misaligned");
+    return MPDATA_OK;
+}
+
+int check_ufield(const void* a, const char* what, const mpdata_umesh* m)
+{
+    if (!a) return fail(MPDATA_EINVAL, "%s is NULL", what);
+    if (!aligned(a, uelem(m))) return fail(MPDATA_EINVAL, "%s is not aligned to its element size", what);
+    return MPDATA_OK;
+}
+
+template <class T>
+int ustep(const mpdata_umesh* m, const void* psi, void* out, const void* vn, const void* w, const void* rho,
+          hipStream_t st)
+{
+    mpdata::unstructured::UArgs<T> a;
+    a.edge_nodes = m->edge_nodes;
+    a.node_ptr = m->node_ptr;
+    a.node_edges = m->node_edges;
+    a.node_sign = m->node_sign;
+    a.vol = (const T*)m->dual_volume;
+    a.psi = (const T*)psi;
+    a.vn = (const T*)vn;
+    a.w = (const T*)w;
+    a.rho = (const T*)rho;
+    a.out = (T*)out;
+    a.pivbz = (T)m->pivbz;
+    a.n_nodes = m->n_nodes;
+    a.nz = m->nz;
+    Timed tm(MPDATA_KERNEL_USTEP, st);
+    const unsigned blocks = (unsigned)(((m->n_nodes + 3) / 4 + 7) / 8 * 8);   // a wave per node, 8 | blocks
+    mpdata::unstructured::k_ustep<T><<<blocks, 256, 0, st>>>(a);
+    return launch_status("unstructured step");
+}
+
+int ustep_checked(const mpdata_umesh* m, const void* psi, void* out, const void* vn, const void* w,
+                  const void* rho, hipStream_t st)
+{
+    return m->dtype == MPDATA_F64 ? ustep<double>(m, psi, out, vn, w, rho, st)
+                                  : ustep<float>(m, psi, out, vn, w, rho, st);
+}
+
+int validate_ucall(const mpdata_umesh* m, const void* psi, const void* vn, const void* w, const void* rho)
+{
+    if (int rc = validate_umesh(m)) return rc;
+    if (int rc = check_ufield(psi, "psi", m)) return rc;
+    if (m->n_edges > 0)
+        if (int rc = check_ufield(vn, "vn", m)) return rc;
+    if (w && !aligned(w, uelem(m))) return fail(MPDATA_EINVAL, "w is not aligned to its element size");
+    return check_ufield(rho, "rho", m);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -911,6 +986,44 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
 extern "C" {
 
 const char* mpdata_last_error(void) { return g_err.c_str(); }
+
+int mpdata_ustep(const mpdata_umesh* m, const void* psi_in, void* psi_out, const void* vn, const void* w,
+                 const void* rho, void* stream)
+{
+    if (int rc = validate_ucall(m, psi_in, vn, w, rho)) return rc;
+    if (int rc = check_ufield(psi_out, "psi_out", m)) return rc;
+    if (psi_in == psi_out) return fail(MPDATA_EINVAL, "psi_out must not alias psi_in");
+    if (int rc = ustep_checked(m, psi_in, psi_out, vn, w, rho, (hipStream_t)stream)) return rc;
+    return ok();
+}
+
+size_t mpdata_uworkspace_bytes(const mpdata_umesh* m)
+{
+    if (validate_umesh(m) != MPDATA_OK) return 0;
+    return (((size_t)m->n_nodes * m->nz * uelem(m)) + 255) & ~(size_t)255;
+}
+
+int mpdata_urun(const mpdata_umesh* m, int32_t nsteps, void* psi, const void* vn, const void* w, const void* rho,
+                void* ws, size_t ws_bytes, void* stream)
+{
+    if (int rc = validate_ucall(m, psi, vn, w, rho)) return rc;
+    if (nsteps < 0) return fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps);
+    if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
+    const size_t need = mpdata_uworkspace_bytes(m);
+    if (ws_bytes < need) return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    void* cur = psi;
+    for (int s = 0; s < nsteps; ++s) {
+        void* nxt = cur == psi ? ws : psi;
+        if (int rc = ustep_checked(m, cur, nxt, vn, w, rho, st)) return rc;
+        cur = nxt;
+    }
+    if (cur != psi) {
+        hipError_t e = hipMemcpyAsync(psi, cur, (size_t)m->n_nodes * m->nz * uelem(m), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail(MPDATA_EDEVICE, "final copy: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
 
 int mpdata_timing_enable(int32_t on)
 {
@@ -930,7 +1043,7 @@ int mpdata_timing_enable(int32_t on)
 
 int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches)
 {
-    if (kind < 0 || kind > 2) return fail(MPDATA_EINVAL, "timing kind %d is not an MPDATA_KERNEL_* value", kind);
+    if (kind < 0 || kind > 3) return fail(MPDATA_EINVAL, "timing kind %d is not an MPDATA_KERNEL_* value", kind);
     if (!total_ms || !launches) return fail(MPDATA_EINVAL, "output pointers must not be NULL");
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double sum = 0.0;
