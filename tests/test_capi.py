@@ -137,3 +137,25 @@ def test_batched_workspace_and_validation():
     # 2 x 2^30 donor-pass blocks (64 x 4 columns x 16 levels each) exceed one launch
     assert _batch_ws(mp, [(64, 4, 16, 1 << 30), (64, 4, 16, 1 << 30)]) == 0
     assert b"blocks" in mp.lib().mpdata_last_error()
+
+
+def test_unstructured_validation():
+    mp = _mp()
+    lib = mp.lib()
+    m = mp.UMesh(10, 15, 4, mp.MPDATA_F64, 0.0, 256, 256, 256, 256, 256)
+    assert lib.mpdata_uworkspace_bytes(ctypes.byref(m)) == (10 * 4 * 8 + 255) // 256 * 256
+    for field, val in (("n_nodes", 0), ("nz", 0), ("n_edges", -1), ("dtype", 7)):
+        bad = mp.UMesh(10, 15, 4, mp.MPDATA_F64, 0.0, 256, 256, 256, 256, 256)
+        setattr(bad, field, val)
+        assert lib.mpdata_uworkspace_bytes(ctypes.byref(bad)) == 0
+    bad = mp.UMesh(10, 15, 4, mp.MPDATA_F64, float("nan"), 256, 256, 256, 256, 256)
+    assert lib.mpdata_uworkspace_bytes(ctypes.byref(bad)) == 0
+    bad = mp.UMesh(10, 15, 4, mp.MPDATA_F64, 0.0, 0, 256, 256, 256, 256)      # edge table missing
+    assert lib.mpdata_uworkspace_bytes(ctypes.byref(bad)) == 0
+    _no_device()
+    v = ctypes.c_void_p
+    assert lib.mpdata_ustep(ctypes.byref(m), v(512), v(512), v(768), None, v(1024), None) == mp._lib.MPDATA_EINVAL
+    assert b"alias" in lib.mpdata_last_error()
+    assert lib.mpdata_ustep(ctypes.byref(m), v(512), v(2048), None, None, v(1024), None) == mp._lib.MPDATA_EINVAL
+    assert lib.mpdata_urun(ctypes.byref(m), 2, v(512), v(768), None, v(1024), v(4096), 16, None) == \
+        mp._lib.MPDATA_ENOMEM
