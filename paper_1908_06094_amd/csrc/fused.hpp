@@ -29,13 +29,15 @@
 //     (vmcnt counts loads and stores in order) never waits for a store;
 //   * coalesced, i-fastest HBM rows (512 B in FP64, 128 B in FP32).
 //
-// Arithmetic differs from the scheme's literal order in one place: the
+// Arithmetic differs from the scheme's literal order in two places.  The
 // antidiffusive velocity (|U| - U^2/Gf) A - (U/Gf)(Vb_1 B_1 + Vb_2 B_2),
 // with A and B ratios over the pair sums, is evaluated over one common
-// denominator (one IEEE division per face instead of four), and the two beta
-// ratios of a cell share one division.  In FP64 this changes results by a few
-// ulp.  In FP32 (where the product of three guarded denominators could
-// underflow) the ratios are taken one by one.
+// denominator (one division per face instead of four), and the two beta
+// ratios of a cell share one division.  FP64 quotients come from the
+// reciprocal with Newton refinement (div_nr, within an ulp of the IEEE
+// quotient).  In FP64 this changes results by a few ulp.  In FP32 (where the
+// product of three guarded denominators could underflow) the ratios are
+// taken one by one.
 #pragma once
 
 #include "common.hpp"
@@ -100,6 +102,23 @@ __device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_
 //   vs1/vs2 the sums of the four transverse face velocities (Vb = vs / 4)
 //   gsum    G(left) + G(right) (Gf = gsum / 2), u the face velocity
 // ---------------------------------------------------------------------------
+// FP64 quotient from the hardware reciprocal refined by two Newton steps and
+// one residual correction (Markstein's scheme): within an ulp of the IEEE
+// quotient, without the scaling and special-case steps of the IEEE division
+// sequence.  Every denominator here is a normal positive number (pair sums
+// guarded by eps, products of them, G).
+__device__ __forceinline__ double div_nr(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    const double q = n * r;
+    return __builtin_fma(r, __builtin_fma(-d, q, n), q);
+}
+__device__ __forceinline__ float div_nr(float n, float d) { return n / d; }
+
 __device__ __forceinline__ double antidiff_face(double n0, double d0, double n1, double d1, double n2, double d2,
                                                 double vs1, double vs2, double gsum, double u)
 {
@@ -109,7 +128,7 @@ __device__ __forceinline__ double antidiff_face(double n0, double d0, double n1,
     const double au = u < 0.0 ? -u : u;
     const double t1 = ((au * gsum - 2.0 * (u * u)) * n0) * d12;
     const double t2 = (0.25 * u) * d0 * (vs1 * n1 * d2 + vs2 * n2 * d1);
-    return (t1 - t2) / ((gsum * d0) * d12);
+    return div_nr(t1 - t2, (gsum * d0) * d12);
 }
 
 __device__ __forceinline__ float antidiff_face(float n0, float d0, float n1, float d1, float n2, float d2,
@@ -129,7 +148,7 @@ __device__ __forceinline__ void beta_pair(T hi, T lo, T phi, T g, T fin, T fout,
 {
     const double a = (double)fin + eps;
     const double b = (double)fout + eps;
-    const double r = 1.0 / (a * b);
+    const double r = div_nr(1.0, a * b);
     bup = (T)(((double)((hi - phi) * g) * b) * r);
     bdn = (T)(((double)((phi - lo) * g) * a) * r);
 }
@@ -438,7 +457,7 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
             const T fy_p_dn = S.fy[par ^ 1][dn][lane];
             const T fx_p_l = lane_prev(fx_p);      // every lane: DPP needs its source lanes active
             const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
-            st_upd = P.phi - div / P.g;            // plane k-1, stored by the next step
+            st_upd = P.phi - div_nr(div, P.g);     // plane k-1, stored by the next step
             st_ulz = ulz;
             st_ulx = ulx;
             st_uly = uly;
