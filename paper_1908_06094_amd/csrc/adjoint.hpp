@@ -427,6 +427,63 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
 // faces come from the stencil offsets; every candidate's actual inputs are
 // recomputed through the halo rules and compared with x, so wrap, clamp and
 // tiny grids (where one cell fills several input positions) are exact.
+// dJ/dphi at cell x from the faces along axis A (the general path of
+// k_adj_antidiff2): the distinct faces y whose 10 stencil positions (L, R,
+// L+-t1, R+-t1, L+-t2, R+-t2 after the halo rule) include x, each position
+// that is x adding that position's partial derivative.
+template <int A>
+__device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const int (&Yt)[3][3],
+                                                            const int (&Tt)[3][3][3], const Cell& c,
+                                                            const double* __restrict__ slots, long long field)
+{
+    constexpr int t1 = A == 0 ? 1 : 0, t2 = A == 2 ? 1 : 2;
+    // stencil offsets of face (A, y) relative to its left cell, and their slots
+    int off[10][3], slot_of[10];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        off[e][0] = off[e][1] = off[e][2] = 0;
+        off[e][A] = e;
+        slot_of[e] = e == 1 ? 0 : 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int n = 2 + 4 * q + 2 * h + e;
+                off[n][0] = off[n][1] = off[n][2] = 0;
+                off[n][A] = e;
+                off[n][q == 0 ? t1 : t2] = h == 0 ? 1 : -1;
+                slot_of[n] = 2 + 2 * q + h;
+            }
+    const int xc[3] = {c.i, c.j, c.k};
+    const int nA = extent(g, A), clA = closed(g, A);
+    const double* sA = slots + (long long)A * kSlots * field;
+    double acc = 0.0;
+    long long seen[10];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+        // candidate face y = x - off[m] (mapped)
+        const int yi = Yt[0][off[m][0] + 1], yj = Yt[1][off[m][1] + 1], yk = Yt[2][off[m][2] + 1];
+        const long long y = (long long)yk * g.sz + (long long)yj * g.sy + yi;
+        seen[m] = y;
+        bool dup = false;
+#pragma unroll
+        for (int s2 = 0; s2 < m; ++s2) dup = dup || seen[s2] == y;
+        const int ya = A == 0 ? yi : (A == 1 ? yj : yk);
+        if (dup || (clA && ya >= nA - 1)) continue;     // counted already / wall: U~ is the constant 0
+#pragma unroll
+        for (int e = 0; e < 10; ++e) {
+            const bool hit = Tt[0][off[m][0] + 1][off[e][0] + 1] == xc[0] &&
+                             Tt[1][off[m][1] + 1][off[e][1] + 1] == xc[1] &&
+                             Tt[2][off[m][2] + 1][off[e][2] + 1] == xc[2];
+            if (hit) acc += sA[slot_of[e] * field + y];
+        }
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
                                                        double* __restrict__ lphi, double* __restrict__ lu,
                                                        double* __restrict__ lv, double* __restrict__ lw)
@@ -494,58 +551,28 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
         return;
     }
 
-    // The loops inside the axis loop are unrolled so that the small tables
-    // and the seen lists live in registers (indexed by compile-time
-    // constants); the axis loop itself stays a loop (its body is large).
-    double acc = 0.0;
-#pragma unroll 1
-    for (int a = 0; a < 3; ++a) {
-        int tr[2];
-        {
-            int n = 0;
-            for (int t = 0; t < 3; ++t)
-                if (t != a) tr[n++] = t;
-        }
-        // input offsets of face (a, y): L, R, L+-t1, R+-t1, L+-t2, R+-t2
-        int off[10][3];
-        int slot_of[10];
-        {
-            int n = 0;
-            for (int e = 0; e < 2; ++e) {
-                off[n][0] = off[n][1] = off[n][2] = 0;
-                off[n][a] = e;
-                slot_of[n] = e == 1 ? 0 : 1;
-                ++n;
-            }
-            for (int q = 0; q < 2; ++q)
-                for (int sg = 1; sg >= -1; sg -= 2)
-                    for (int e = 0; e < 2; ++e) {
-                        off[n][0] = off[n][1] = off[n][2] = 0;
-                        off[n][a] = e;
-                        off[n][tr[q]] = sg;
-                        slot_of[n] = 2 + 2 * q + (sg > 0 ? 0 : 1);
-                        ++n;
-                    }
-        }
-        long long seen[10];
+    // General path (a closed end within two cells on some axis).  The halo
+    // rule maps each coordinate independently, so the candidate faces and
+    // their stencil positions are looked up in per-axis tables of mapped
+    // coordinates: Y[b][o] = nbr(x_b - o) and T[b][o1][o2] = nbr(Y[b][o1] + o2)
+    // for offsets o, o1, o2 in {-1, 0, 1}.
+    int Yt[3][3], Tt[3][3][3];
+    {
+        const int xc[3] = {c.i, c.j, c.k};
 #pragma unroll
-        for (int m = 0; m < 10; ++m) {
-            const Pt yp = mapped(g, c.i - off[m][0], c.j - off[m][1], c.k - off[m][2]);
-            const long long y = yp.q;
-            seen[m] = y;
-            bool dup = false;
+        for (int b = 0; b < 3; ++b) {
+            const int n = extent(g, b), cl = closed(g, b);
 #pragma unroll
-            for (int s2 = 0; s2 < m; ++s2) dup = dup || seen[s2] == y;
-            if (dup) continue;
-            const int yk = yp.k, yj = yp.j, yi = yp.i;
-            if (face_idx(g, a, yi, yj, yk) < 0) continue;   // wall: U~ is the constant 0
-            const double* s = slots + (long long)a * kSlots * field + y;
+            for (int o1 = 0; o1 < 3; ++o1) {
+                Yt[b][o1] = nbr(xc[b] - (o1 - 1), n, cl);
 #pragma unroll
-            for (int e = 0; e < 10; ++e) {
-                if (at(g, yi + off[e][0], yj + off[e][1], yk + off[e][2]) == x) acc += s[slot_of[e] * field];
+                for (int o2 = 0; o2 < 3; ++o2) Tt[b][o1][o2] = nbr(Yt[b][o1] + (o2 - 1), n, cl);
             }
         }
     }
+    double acc = adj_antidiff_general_axis<0>(g, Yt, Tt, c, slots, field) +
+                 adj_antidiff_general_axis<1>(g, Yt, Tt, c, slots, field);
+    acc += adj_antidiff_general_axis<2>(g, Yt, Tt, c, slots, field);
     lphi[x] += acc;
 
     // velocities of x's own faces: face (t, x) is read as the own velocity of
