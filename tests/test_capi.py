@@ -159,3 +159,20 @@ def test_unstructured_validation():
     assert lib.mpdata_ustep(ctypes.byref(m), v(512), v(2048), None, None, v(1024), None) == mp._lib.MPDATA_EINVAL
     assert lib.mpdata_urun(ctypes.byref(m), 2, v(512), v(768), None, v(1024), v(4096), 16, None) == \
         mp._lib.MPDATA_ENOMEM
+
+
+def test_unsupported_combinations():
+    """FP32 adjoints and batched runs of more than 9 passes are refused with
+    MPDATA_EUNSUPPORTED before anything is enqueued."""
+    mp = _mp()
+    lib = mp.lib()
+    _no_device()
+    v = ctypes.c_void_p
+    p32 = mp.problem_for((8, 6, 4), dtype="f32")
+    args = [v(256)] * 5 + [v(512)] + [v(768)] * 3 + [None, None, v(1024), 1 << 40, None]
+    assert lib.mpdata_adjoint(ctypes.byref(p32), 2, 1, *args) == mp._lib.MPDATA_EUNSUPPORTED
+    assert b"FP64" in lib.mpdata_last_error()
+    p = mp.problem_for((1, 1, 1), iters=10)
+    arr = _items(mp, [(64, 32, 20, 1)])
+    assert lib.mpdata_run_batched(ctypes.byref(p), 1, ctypes.cast(arr, ctypes.c_void_p), 2, 0, v(4096), 1 << 40,
+                                  None) in (mp._lib.MPDATA_EUNSUPPORTED, mp._lib.MPDATA_EINVAL)
