@@ -282,13 +282,14 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         const int cj = map_index(gj, geo.ny, geo.closed_y);
         const bool xwall = wall_face(gi, geo.nx, geo.closed_x);
         const bool ywall = wall_face(gj, geo.ny, geo.closed_y);
-        const long long col = (long long)cj * geo.sy + ci;
+        // a plane holds at most 2^30 cells (checked on the host): 32-bit offsets
+        const unsigned col = (unsigned)(cj * (int)geo.sy + ci);
         const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
         // this lane's cell in the tile layout (a writer's cell lies in its own tile)
         const int ttx = ci / kTileX, tty = cj / kTileY;
-        const long long tcol = (long long)(tty * a.tiles_x + ttx) * (kTileX * kTileY) +
-                               (cj - tty * kTileY) * kTileX + (ci - ttx * kTileX);
+        const unsigned tcol = (unsigned)((tty * a.tiles_x + ttx) * (kTileX * kTileY) +
+                                         (cj - tty * kTileY) * kTileX + (ci - ttx * kTileX));
         const long long tplane = tiled_plane<T>(a.tiles_x, a.tiles_y);
 
         // plane loader: cell quantities through the halo rule.  Every load is

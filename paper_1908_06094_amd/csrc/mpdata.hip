@@ -59,6 +59,8 @@ int validate(const mpdata_problem* p)
     if ((long long)p->nx * p->ny * p->nz > kMaxCells)
         return fail(MPDATA_EINVAL, "grid of %lld cells exceeds the supported maximum",
                     (long long)p->nx * p->ny * p->nz);
+    if ((long long)p->nx * p->ny > (1LL << 30))
+        return fail(MPDATA_EINVAL, "a plane of %lld cells exceeds the supported 2^30", (long long)p->nx * p->ny);
     if (p->nz > 65535 || p->ny > 65535 * 4)
         return fail(MPDATA_EINVAL, "ny=%d / nz=%d exceed the launch grid limits (ny <= 262140, nz <= 65535)",
                     p->ny, p->nz);
@@ -643,7 +645,8 @@ int validate_items(const mpdata_problem* c, int n, const mpdata_batch_item* item
     long long donor_blocks = 0;
     for (int i = 0; i < n; ++i) {
         const mpdata_batch_item& it = items[i];
-        if (it.nx < 1 || it.ny < 1 || it.nz < 1 || it.nz > 65535 || it.ny > 65535 * 4)
+        if (it.nx < 1 || it.ny < 1 || it.nz < 1 || it.nz > 65535 || it.ny > 65535 * 4 ||
+            (long long)it.nx * it.ny > (1LL << 30))
             return fail(MPDATA_EINVAL, "item %d: sizes %dx%dx%d out of range", i, it.nx, it.ny, it.nz);
         if (it.ntracers < 1) return fail(MPDATA_EINVAL, "item %d: ntracers=%d must be >= 1", i, it.ntracers);
         const void* req[] = {it.cx, it.cy, it.g, it.psi};
