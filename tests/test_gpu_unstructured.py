@@ -79,3 +79,22 @@ def test_ustep_rejects_bad_calls():
     bad[3, 1] = m.n_nodes + 5
     with pytest.raises(ValueError):
         mp.DeviceMesh(bad, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, 4)
+
+
+def test_benchmark_mesh_full_size():
+    """The benchmark workload itself (O128: 70 144 nodes, 209 864 edges,
+    80 levels), 2 steps, bit for bit against the oracle."""
+    torch = _torch()
+    import paper_1908_06094_amd as mp
+
+    u = octa.octahedral_workload(128, 80)
+    m = u.mesh
+    _say(f"[unstructured] {u.name} full size, 2 steps")
+    want = oracle.urun(2, m.edges, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, u.psi, u.vn, u.w, u.rho,
+                       u.pivbz)
+    dm = mp.DeviceMesh.from_octa(m, u.nz, pivbz=u.pivbz)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    psi = dev(u.psi)
+    mp.urun(dm, psi, dev(u.vn), dev(u.w), dev(u.rho), 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(psi.cpu().numpy(), want)
