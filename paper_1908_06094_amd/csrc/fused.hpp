@@ -432,15 +432,25 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
                 const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
                 T bup, bdn;
                 beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
+                // only min(1, beta) is ever used.  FP64 clamps once per cell
+                // (min(1, a, b) = min(min(1, a), min(1, b)) exactly) and
+                // keeps one min per use; FP32 has a three-operand min.
+                if (sizeof(T) == 8) {
+                    bup = fmn(T(1), bup);
+                    bdn = fmn(T(1), bdn);
+                }
+                auto lim = [](T x, T y) __attribute__((always_inline)) {
+                    return sizeof(T) == 8 ? fmn(x, y) : min3(T(1), x, y);
+                };
                 S.bup[row][lane] = bup;
                 S.bdn[row][lane] = bdn;
                 lds_barrier();
 
                 // ---------------- phase 3a: limited velocities ----------------
                 const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
-                ulx = pos_f(ux) * min3(T(1), bdn, lane_next(bup)) + neg_f(ux) * min3(T(1), bup, lane_next(bdn));
-                uly = pos_f(uy) * min3(T(1), bdn, bup_up) + neg_f(uy) * min3(T(1), bup, bdn_up);
-                ulz = pos_f(uz_p) * min3(T(1), bdn_p, bup) + neg_f(uz_p) * min3(T(1), bup_p, bdn);
+                ulx = pos_f(ux) * lim(bdn, lane_next(bup)) + neg_f(ux) * lim(bup, lane_next(bdn));
+                uly = pos_f(uy) * lim(bdn, bup_up) + neg_f(uy) * lim(bup, bdn_up);
+                ulz = pos_f(uz_p) * lim(bdn_p, bup) + neg_f(uz_p) * lim(bup_p, bdn);
                 bup_p = bup;
                 bdn_p = bdn;
             } else {
