@@ -259,11 +259,20 @@ struct Raw {
     T phi, psin, u, v, w, g;
 };
 
-// March output planes [kb, ke) of one tile of one problem (all threads of
-// the workgroup call this together).
-template <class T, bool LIMIT, bool WRITE_VEL>
-__device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
-                                             const int kb, const int ke)
+// March output planes [kb, ke) of one tile of one problem: the part of
+// one wave, whose rows play role ROLE (all waves of the workgroup march
+// together and meet at the same barriers).
+//   ROLE 0: rows holding outputs; every stage.
+//   ROLE 1: the second halo rows (1 and R-2 of R rows): with the limiter,
+//           the face velocities, bounds and beta, which the neighbouring
+//           output row's limited velocities need, and (row 1) the limited
+//           y flux into row 2; without it, (row 1) the y velocity and flux.
+//   ROLE 2: the outer halo rows (0 and R-1): their loads and LDS slots and,
+//           with the limiter, (row 0) the y-face velocity below row 1,
+//           which row 1's beta needs.
+template <class T, bool LIMIT, bool WRITE_VEL, int ROLE>
+__device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
+                                          const int kb, const int ke)
 {
     constexpr int kLanes = Tile<T>::lanes, kRows = Tile<T>::rows;
     constexpr int kTileX = Tile<T>::tile_x, kTileY = Tile<T>::tile_y;
@@ -308,6 +317,13 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
             B.w = *(has_w ? a.w + qv : a.g + q);
             B.g = a.g[q];
         };
+
+        // Stages this wave runs (see the row roles below).
+        constexpr bool do_upd = ROLE == 0;
+        constexpr bool do_fy = ROLE <= 1;
+        constexpr bool do_beta = LIMIT && ROLE <= 1;
+        constexpr bool do_uy = LIMIT || do_fy;
+        constexpr bool do_uxz = LIMIT ? do_beta : do_upd;
 
         Bank<T> B0{}, B1{}, B2{};
         Raw<T> R{};
@@ -379,105 +395,120 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
             N.upy = N.u + S.u[up][lane];
             N.wpy = N.w + S.w[up][lane];
             N.gpy = N.g + S.g[up][lane];
-            const T px_c_up = S.px[sc][up][lane];
-            const T px_c_dn = S.px[sc][dn][lane];
-            const T vpxdn_c = S.vpx[sc][dn][lane];
             const T phiup_c = S.phi[sc][up][lane];
-            const T pz_up = S.pz[up][lane];
-            const T pz_dn = S.pz[dn][lane];
-            const T vpz_dn = S.vpz[dn][lane];
             const T nphi_c = lane_next(C.phi);
-            const T gx_c = C.g + lane_next(C.g);
 
-            // x face (i+1/2, j, k): transverse y then z
-            const T ux = antidiff_face(nphi_c - C.phi, C.px + eps,
-                                       px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
-                                       N.px - P.px, (N.px + P.px) + eps,
-                                       C.vpx + vpxdn_c, wsx, gx_c, C.u);
-            // y face (i, j+1/2, k): transverse x then z
-            const T py_nx = lane_next(C.py), py_pv = lane_prev(C.py);
-            const T uy = antidiff_face(phiup_c - C.phi, C.py + eps,
-                                       py_nx - py_pv, (py_nx + py_pv) + eps,
-                                       N.py - P.py, (N.py + P.py) + eps,
-                                       C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
-            // z face (i, j, k+1/2): transverse x then y
-            const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
-            const T uz = antidiff_face(N.phi - C.phi, pz_c + eps,
-                                       pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
-                                       pz_up - pz_dn, (pz_up + pz_dn) + eps,
-                                       upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
+            T ux = zero, uy = zero, uz = zero;
+            if (do_uxz) {
+                const T px_c_up = S.px[sc][up][lane];
+                const T px_c_dn = S.px[sc][dn][lane];
+                const T vpxdn_c = S.vpx[sc][dn][lane];
+                const T pz_up = S.pz[up][lane];
+                const T pz_dn = S.pz[dn][lane];
+                const T vpz_dn = S.vpz[dn][lane];
+                const T gx_c = C.g + lane_next(C.g);
+                // x face (i+1/2, j, k): transverse y then z
+                ux = antidiff_face(nphi_c - C.phi, C.px + eps,
+                                   px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
+                                   N.px - P.px, (N.px + P.px) + eps,
+                                   C.vpx + vpxdn_c, wsx, gx_c, C.u);
+                // z face (i, j, k+1/2): transverse x then y
+                const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
+                uz = antidiff_face(N.phi - C.phi, pz_c + eps,
+                                   pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
+                                   pz_up - pz_dn, (pz_up + pz_dn) + eps,
+                                   upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
+            }
+            if (do_uy) {
+                // y face (i, j+1/2, k): transverse x then z
+                const T py_nx = lane_next(C.py), py_pv = lane_prev(C.py);
+                uy = antidiff_face(phiup_c - C.phi, C.py + eps,
+                                   py_nx - py_pv, (py_nx + py_pv) + eps,
+                                   N.py - P.py, (N.py + P.py) + eps,
+                                   C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
+            }
 
-            T ulx, uly, ulz;       // limited velocities: x, y at plane k; z at face k-1/2
+            // limited velocities: x, y at plane k; z at face k-1/2
+            T ulx = ux, uly = uy, ulz = uz_p;
             if (LIMIT) {
-                const T fpy = pos_f(uy) * C.phi;
-                const T fmy = neg_f(uy) * phiup_c;
+                T fpy = zero, fmy = zero;
+                if (do_uy) {
+                    fpy = pos_f(uy) * C.phi;
+                    fmy = neg_f(uy) * phiup_c;
+                    S.fpy[row][lane] = fpy;
+                    S.fmy[row][lane] = fmy;
+                }
                 S.mx[row][lane] = C.mx;
                 S.mn[row][lane] = C.mn;
-                S.fpy[row][lane] = fpy;
-                S.fmy[row][lane] = fmy;
                 lds_barrier();
 
                 // ---------------- phase 2: bounds, in/out, beta at plane k ----------------
-                const T hi = fmx(fmx(C.mx, fmx(lane_next(C.mx), lane_prev(C.mx))),
-                                 fmx(fmx(S.mx[up][lane], S.mx[dn][lane]), fmx(P.mx, N.mx)));
-                const T lo = fmn(fmn(C.mn, fmn(lane_next(C.mn), lane_prev(C.mn))),
-                                 fmn(fmn(S.mn[up][lane], S.mn[dn][lane]), fmn(P.mn, N.mn)));
-                const T fpx = pos_f(ux) * C.phi;
-                const T fmx_ = neg_f(ux) * nphi_c;
-                const T fpz = pos_f(uz) * C.phi;
-                const T fmz = neg_f(uz) * N.phi;
-                const T fpz_l = pos_f(uz_p) * P.phi;
-                const T fmz_l = neg_f(uz_p) * C.phi;
-                const T fin = ((lane_prev(fpx) - fmx_) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
-                const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
-                T bup, bdn;
-                beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
-                // only min(1, beta) is ever used.  FP64 clamps once per cell
-                // (min(1, a, b) = min(min(1, a), min(1, b)) exactly) and
-                // keeps one min per use; FP32 has a three-operand min.
-                if (sizeof(T) == 8) {
-                    bup = fmn(T(1), bup);
-                    bdn = fmn(T(1), bdn);
+                T bup = zero, bdn = zero;
+                if (do_beta) {
+                    const T hi = fmx(fmx(C.mx, fmx(lane_next(C.mx), lane_prev(C.mx))),
+                                     fmx(fmx(S.mx[up][lane], S.mx[dn][lane]), fmx(P.mx, N.mx)));
+                    const T lo = fmn(fmn(C.mn, fmn(lane_next(C.mn), lane_prev(C.mn))),
+                                     fmn(fmn(S.mn[up][lane], S.mn[dn][lane]), fmn(P.mn, N.mn)));
+                    const T fpx = pos_f(ux) * C.phi;
+                    const T fmx_ = neg_f(ux) * nphi_c;
+                    const T fpz = pos_f(uz) * C.phi;
+                    const T fmz = neg_f(uz) * N.phi;
+                    const T fpz_l = pos_f(uz_p) * P.phi;
+                    const T fmz_l = neg_f(uz_p) * C.phi;
+                    const T fin = ((lane_prev(fpx) - fmx_) + (S.fpy[dn][lane] - fmy)) + (fpz_l - fmz);
+                    const T fout = ((fpx - lane_prev(fmx_)) + (fpy - S.fmy[dn][lane])) + (fpz - fmz_l);
+                    beta_pair<T>(hi, lo, C.phi, C.g, fin, fout, a.eps, bup, bdn);
+                    // only min(1, beta) is ever used.  FP64 clamps once per cell
+                    // (min(1, a, b) = min(min(1, a), min(1, b)) exactly) and
+                    // keeps one min per use; FP32 has a three-operand min.
+                    if (sizeof(T) == 8) {
+                        bup = fmn(T(1), bup);
+                        bdn = fmn(T(1), bdn);
+                    }
+                    S.bup[row][lane] = bup;
+                    S.bdn[row][lane] = bdn;
                 }
                 auto lim = [](T x, T y) __attribute__((always_inline)) {
                     return sizeof(T) == 8 ? fmn(x, y) : min3(T(1), x, y);
                 };
-                S.bup[row][lane] = bup;
-                S.bdn[row][lane] = bdn;
                 lds_barrier();
 
                 // ---------------- phase 3a: limited velocities ----------------
-                const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
-                ulx = pos_f(ux) * lim(bdn, lane_next(bup)) + neg_f(ux) * lim(bup, lane_next(bdn));
-                uly = pos_f(uy) * lim(bdn, bup_up) + neg_f(uy) * lim(bup, bdn_up);
-                ulz = pos_f(uz_p) * lim(bdn_p, bup) + neg_f(uz_p) * lim(bup_p, bdn);
-                bup_p = bup;
-                bdn_p = bdn;
-            } else {
-                ulx = ux;
-                uly = uy;
-                ulz = uz_p;
+                if (do_fy) {
+                    const T bup_up = S.bup[up][lane], bdn_up = S.bdn[up][lane];
+                    uly = pos_f(uy) * lim(bdn, bup_up) + neg_f(uy) * lim(bup, bdn_up);
+                }
+                if (do_upd) {
+                    ulx = pos_f(ux) * lim(bdn, lane_next(bup)) + neg_f(ux) * lim(bup, lane_next(bdn));
+                    ulz = pos_f(uz_p) * lim(bdn_p, bup) + neg_f(uz_p) * lim(bup_p, bdn);
+                    bup_p = bup;
+                    bdn_p = bdn;
+                }
             }
 
             // ---------------- phase 3b: donor-cell update of plane k-1 ----------------
             const int par = t & 1;
-            const T fx_c = pos_f(ulx) * C.phi + neg_f(ulx) * nphi_c;
-            const T fy_c = pos_f(uly) * C.phi + neg_f(uly) * phiup_c;
-            S.fy[par][row][lane] = fy_c;
-            const T fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
-            const T fy_p_dn = S.fy[par ^ 1][dn][lane];
-            const T fx_p_l = lane_prev(fx_p);      // every lane: DPP needs its source lanes active
-            const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
-            st_upd = P.phi - div_nr(div, P.g);     // plane k-1, stored by the next step
-            st_ulz = ulz;
-            st_ulx = ulx;
-            st_uly = uly;
-            fz_pp = fz_h;
+            if (do_fy) {
+                const T fy_c = pos_f(uly) * C.phi + neg_f(uly) * phiup_c;
+                S.fy[par][row][lane] = fy_c;
+                if (do_upd) {
+                    const T fx_c = pos_f(ulx) * C.phi + neg_f(ulx) * nphi_c;
+                    const T fz_h = pos_f(ulz) * P.phi + neg_f(ulz) * C.phi;     // face k-1/2
+                    const T fy_p_dn = S.fy[par ^ 1][dn][lane];
+                    const T fx_p_l = lane_prev(fx_p);      // every lane of the wave: DPP reads its neighbours
+                    const T div = ((fx_p - fx_p_l) + (fy_p - fy_p_dn)) + (fz_h - fz_pp);
+                    st_upd = P.phi - div_nr(div, P.g);     // plane k-1, stored by the next step
+                    st_ulz = ulz;
+                    st_ulx = ulx;
+                    st_uly = uly;
+                    fz_pp = fz_h;
+                    fx_p = fx_c;
+                    fy_p = fy_c;
+                }
+            }
+            if (do_uxz) uz_p = uz;
             wsx = N.wpx + C.wpx;
             wsy = N.wpy + C.wpy;
-            fx_p = fx_c;
-            fy_p = fy_c;
-            uz_p = uz;
             if (!LIMIT) lds_barrier();   // phase-0 slots are rewritten next; with the limiter the
                                          // phase-2 and phase-3 barriers already separate them
         };
@@ -491,6 +522,30 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
         flush(t_last);
         lds_barrier();   // the next segment rewrites every slot
     }
+}
+
+// One tile's march, each wave in the role of its rows (a wave holding
+// several rows takes the role of the row that needs most).  FP32 runs every
+// wave in role 0: there only two waves of twelve hold no output row, and
+// the kernel with three loop bodies spills more of its 80 registers.
+template <class T, bool LIMIT, bool WRITE_VEL>
+__device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
+                                             const int kb, const int ke)
+{
+    constexpr int kRows = Tile<T>::rows, kRowsPerWave = 64 / Tile<T>::lanes;
+    static_assert(kHalo == 2, "the row roles assume a halo of 2");
+    if (sizeof(T) == 4) {
+        pass_rows<T, LIMIT, WRITE_VEL, 0>(geo, a, S, tile, kb, ke);
+        return;
+    }
+    const int r_lo = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) * kRowsPerWave);
+    const int r_hi = r_lo + kRowsPerWave - 1;
+    if (r_lo <= kRows - 3 && r_hi >= 2)
+        pass_rows<T, LIMIT, WRITE_VEL, 0>(geo, a, S, tile, kb, ke);
+    else if (r_lo <= kRows - 2 && r_hi >= 1)
+        pass_rows<T, LIMIT, WRITE_VEL, 1>(geo, a, S, tile, kb, ke);
+    else
+        pass_rows<T, LIMIT, WRITE_VEL, 2>(geo, a, S, tile, kb, ke);
 }
 
 // Logical workgroup id: the dispatcher deals workgroups round-robin over the
