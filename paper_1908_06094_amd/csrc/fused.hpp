@@ -27,7 +27,9 @@
 //     unconditional, and a step's results are stored at the start of the
 //     following step, before its prefetch, so that waiting for a prefetch
 //     (vmcnt counts loads and stores in order) never waits for a store;
-//   * coalesced, i-fastest HBM rows (512 B in FP64, 128 B in FP32).
+//   * coalesced, i-fastest HBM rows (512 B in FP64, 128 B in FP32);
+//   * in FP64 each wave runs only the stages its tile row feeds (the halo
+//     rows skip the update, the outer ones nearly everything: pass_rows).
 //
 // Arithmetic differs from the scheme's literal order in two places.  The
 // antidiffusive velocity (|U| - U^2/Gf) A - (U/Gf)(Vb_1 B_1 + Vb_2 B_2),
