@@ -171,6 +171,17 @@ def time_batched(mp, torch, dev, steps=20, reps=3):
             "unit": "tracer-cell updates/s", "ms_per_step": round(t * 1e3 / steps, 4)}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def time_unstructured(mp, torch, dev, steps=20, cpu=True):
     """The paper's own dwarf: the edge-based donor-cell step on an octahedral
     grid of 70 144 nodes (O128: 209 864 edges) x 80 levels, FP64 (solid-body
@@ -366,8 +377,26 @@ def main():
         cpu_s = time.perf_counter() - t1
         cpu = {"value": round(w.cells * n / cpu_s, 1), "unit": "grid-point updates/s",
                "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{n} full step(s) of {w.name} (FP64, plain C, OpenMP over levels), {cpu_s:.1f} s"}
+               "sample": f"{n} full step(s) of {w.name} (FP64, plain C, OpenMP over levels), {cpu_s:.1f} s",
+               "cpu_model": cpu_model(), "cpus_visible": len(os.sched_getaffinity(0))}
         log(f"[bench] cpu oracle: {n} steps in {cpu_s:.1f} s")
+        # one thread, on the lowest levels of the same grid (same winds and
+        # tracer; the oracle's cost per cell does not depend on the level count)
+        nz1 = min(w.shape[0], 4)
+        rp1 = oracle.RefProblem(w.shape[2], w.shape[1], nz1, bc=w.bc, iters=w.iters, limiter=w.limiter)
+        threads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        try:
+            sl = (slice(0, nz1),)
+            t1 = time.perf_counter()
+            oracle.step(rp1, src[sl], w.cx[sl], w.cy[sl], w.cz[sl], w.g[sl])
+            one_s = time.perf_counter() - t1
+        finally:
+            oracle.set_num_threads(threads)
+        cells1 = w.shape[2] * w.shape[1] * nz1
+        cpu["one_thread"] = {"value": round(cells1 / one_s, 1), "unit": "grid-point updates/s",
+                             "sample": f"1 step of levels 0-{nz1 - 1} of {w.name}, {one_s:.2f} s"}
+        log(f"[bench] cpu oracle, 1 thread: {cells1} cells in {one_s:.2f} s")
         # the same n steps on the GPU from the same start: errors against the oracle
         x = torch.from_numpy(w.psi).to(dev, tdt)
         m0 = mp.mass(x, g, bc=w.bc)

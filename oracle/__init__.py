@@ -18,6 +18,7 @@ from .ref import (  # noqa: F401
     lib_path,
     mass,
     num_threads,
+    set_num_threads,
     run,
     step,
 )

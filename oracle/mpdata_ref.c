@@ -462,6 +462,15 @@ int ref_num_threads(void)
 #endif
 }
 
+void ref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Reverse (adjoint) sweep                                            */
 /*                                                                    */

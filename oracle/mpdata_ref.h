@@ -97,6 +97,8 @@ int ref_adjoint(const ref_problem* p, int32_t nsteps, const double* psi0,
 
 /* Threads the oracle's parallel loops use (OpenMP). */
 int ref_num_threads(void);
+/* Threads of later calls (OpenMP builds; n >= 1). */
+void ref_set_num_threads(int n);
 
 /* ------------------------------------------------------------------------
  * Edge-based donor-cell step on an unstructured mesh (the paper's own MPDATA

@@ -98,6 +98,8 @@ def _load():
         lib.ref_adjoint.restype = ctypes.c_int
         lib.ref_num_threads.argtypes = []
         lib.ref_num_threads.restype = ctypes.c_int
+        lib.ref_set_num_threads.argtypes = [ctypes.c_int]
+        lib.ref_set_num_threads.restype = None
         _I32 = ctypes.POINTER(ctypes.c_int32)
         _I8 = ctypes.POINTER(ctypes.c_int8)
         lib.ref_ustep.argtypes = [ctypes.POINTER(_UMesh), _I32, _I32, _I32, _I8] + [_P] * 6
@@ -194,6 +196,11 @@ def mass(p: RefProblem, psi, g) -> float:
 
 def num_threads() -> int:
     return int(_load().ref_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later calls (its OpenMP loops)."""
+    _load().ref_set_num_threads(int(n))
 
 
 def adjoint(p: RefProblem, nsteps: int, psi0, cx, cy, cz, g, seed):
