@@ -67,13 +67,16 @@ __device__ __forceinline__ int first_min3(double x, double y)
 }
 
 // ---------------------------------------------------------------------------
-// Donor-cell pass out = phi - div(F)/G:  lout -> lphi (+=), lvel (+=)
+// Donor-cell pass out = phi - div(F)/G:  lout -> lphi, lvel (each += or, for
+// the first contribution a buffer receives, =; an assigned velocity adjoint
+// is 0 at a closed wall's unused slot)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restrict__ phi, const double* __restrict__ u,
                                                    const double* __restrict__ v, const double* __restrict__ w,
                                                    const double* __restrict__ gm, const double* __restrict__ lout,
                                                    double* __restrict__ lphi, double* __restrict__ lu,
-                                                   double* __restrict__ lv, double* __restrict__ lw)
+                                                   double* __restrict__ lv, double* __restrict__ lw, int assign_phi,
+                                                   int assign_vel)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
@@ -83,8 +86,9 @@ __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restri
     const double mu_c = lout[c.q] / gm[c.q];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        // own face c+1/2: the flux leaves c and enters r
+        // own face c+1/2 (its slot is c's): the flux leaves c and enters r
         long long fo = face_idx(g, a, c.i, c.j, c.k);
+        double lvo = 0.0;
         if (fo >= 0 && vel[a] != nullptr) {
             int r[3] = {c.i, c.j, c.k};
             r[a] += 1;
@@ -92,7 +96,11 @@ __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restri
             const double lamf = lout[qr] / gm[qr] - mu_c;
             const double vv = vel[a][fo];
             acc += ppos(vv) * lamf;
-            if (lvel[a]) lvel[a][fo] += (stp(vv) * phi[c.q] + stn(vv) * phi[qr]) * lamf;
+            lvo = (stp(vv) * phi[c.q] + stn(vv) * phi[qr]) * lamf;
+        }
+        if (lvel[a]) {
+            if (assign_vel) lvel[a][c.q] = lvo;
+            else if (fo >= 0 && vel[a] != nullptr) lvel[a][fo] += lvo;
         }
         // left face c-1/2: c is the right cell of the flux
         int l[3] = {c.i, c.j, c.k};
@@ -104,7 +112,8 @@ __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restri
             acc += pneg(vel[a][fl]) * lamf;
         }
     }
-    lphi[c.q] += acc;
+    if (assign_phi) lphi[c.q] = acc;
+    else lphi[c.q] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -221,12 +230,13 @@ __global__ void __launch_bounds__(256) k_bounds(Geo g, const double* __restrict_
     code[2 * c.q + 1] = (unsigned char)an;
 }
 
-// (lmx, lmn) -> lpsin (+=), lphi (+=): each cell x collects from the distinct
-// cells whose cross contains it, where x is the recorded first maximal /
-// minimal entry.
+// (lmx, lmn) -> lpsin (+=, or = for its first contribution), lphi (+=): each
+// cell x collects from the distinct cells whose cross contains it, where x is
+// the recorded first maximal / minimal entry.
 __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* __restrict__ code,
                                                     const double* __restrict__ lmx, const double* __restrict__ lmn,
-                                                    double* __restrict__ lpsin, double* __restrict__ lphi)
+                                                    double* __restrict__ lpsin, double* __restrict__ lphi,
+                                                    int assign_psin)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
@@ -246,7 +256,8 @@ __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* 
         if (cross_entry(g, y.i, y.j, y.k, am % 7) == c.q) (am < 7 ? gp : gf) += lmx[y.q];
         if (cross_entry(g, y.i, y.j, y.k, an % 7) == c.q) (an < 7 ? gp : gf) += lmn[y.q];
     }
-    lpsin[c.q] += gp;
+    if (assign_psin) lpsin[c.q] = gp;
+    else lpsin[c.q] += gp;
     lphi[c.q] += gf;
 }
 
@@ -486,7 +497,8 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
 
 __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
                                                        double* __restrict__ lphi, double* __restrict__ lu,
-                                                       double* __restrict__ lv, double* __restrict__ lw)
+                                                       double* __restrict__ lv, double* __restrict__ lw,
+                                                       int assign_vel)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
@@ -546,7 +558,8 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                 // face (t, x) is read by faces (a, y) at y = x, x - a, x + t, x - a + t
                 accv += (s6[x] + s6[x + da]) + (s6[x + dt] + s6[x + da + dt]);
             }
-            lvel[t][x] += accv;
+            if (assign_vel) lvel[t][x] = accv;
+            else lvel[t][x] += accv;
         }
         return;
     }
@@ -582,7 +595,10 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
     for (int t = 0; t < 3; ++t) {
         if (!lvel[t]) continue;
         const long long fx = face_idx(g, t, c.i, c.j, c.k);
-        if (fx < 0) continue;
+        if (fx < 0) {
+            if (assign_vel) lvel[t][x] = 0.0;   // a closed wall's unused slot
+            continue;
+        }
         double accv = slots[((long long)t * kSlots + 8) * field + x];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -630,7 +646,8 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                 if (hits) accv += hits * slots[((long long)a * kSlots + 6 + q) * field + y];
             }
         }
-        lvel[t][fx] += accv;
+        if (assign_vel) lvel[t][fx] = accv;
+        else lvel[t][fx] += accv;
     }
 }
 

@@ -249,7 +249,8 @@ int step_stages(const mpdata_problem* p, const T* psin, T* psout, const T* cx, c
             mpdata::stages::k_beta<T><<<grd, blk, 0, st>>>(g, eps_d, psin, phi, vq[0], vq[1], vq[2], gm,
                                                           b.bup, b.bdn);
             if (int rc = launch_status("limiter coefficients")) return rc;
-            mpdata::stages::k_limit<T><<<grd, blk, 0, st>>>(g, vq[0], vq[1], vq[2], b.bup, b.bdn);
+            mpdata::stages::k_limit<T><<<grd, blk, 0, st>>>(g, vq[0], vq[1], vq[2], vq[0], vq[1], vq[2], b.bup,
+                                                           b.bdn);
             if (int rc = launch_status("limited velocities")) return rc;
         }
         mpdata::stages::k_donor<T><<<grd, blk, 0, st>>>(g, phi, vq[0], vq[1], vq[2], gm, nxt);
@@ -464,11 +465,13 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     L.K = K;
     L.segs = nsteps > 0 ? (nsteps + K - 1) / K : 1;
     L.M = p->iters;
-    // checkpoints + segment states + per pass (phi, U~ x3, V x3, beta x2, mx,
-    // mn, extremal-entry codes) + 18 adjoint fields (cur, prev, psin, V x3,
-    // Vprev x3, U~ x3, beta x2, lin, lout, lmx, lmn) + antidiffusive slots (27)
-    // + a forward step's workspace + a zero field and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)12 * L.M + 18 + 27 + kStepFields + 2;
+    // checkpoints + segment states + per corrective pass the step's recomputed
+    // intermediates (the pass's input iterate, U~ x3, V x3, beta x2, mx, mn,
+    // extremal-entry codes) + the step's output + 18 adjoint fields (cur,
+    // prev, psin, V x3, Vprev x3, U~ x3, beta x2, lin, lout, lmx, lmn) +
+    // antidiffusive slots (27) + a forward step's workspace + a zero field
+    // and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)12 * (L.M - 1) + 1 + 18 + 27 + kStepFields + 2;
     return L;
 }
 
@@ -487,11 +490,13 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (auto& f : ckpt) f = field();
     for (auto& f : seg) f = field();
     const int M = L.M;
+    // the intermediates of the step being reversed, pass m = 2..M (phis[m -
+    // 1] is the pass's input iterate, phis[M] the step's output)
     std::vector<double*> phis(M + 1, nullptr), ut(3 * (M + 1), nullptr), vl(3 * (M + 1), nullptr),
         bu(M + 1, nullptr), bd(M + 1, nullptr), mx(M + 1, nullptr), mn(M + 1, nullptr);
     std::vector<unsigned char*> code(M + 1, nullptr);   // 2 bytes per cell in a field of 8
-    for (int m = 1; m <= M; ++m) {
-        phis[m] = field();
+    for (int m = 2; m <= M; ++m) {
+        phis[m - 1] = field();
         bu[m] = field();
         bd[m] = field();
         mx[m] = field();
@@ -500,8 +505,10 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
         for (int a = 0; a < 3; ++a) {
             ut[3 * m + a] = field();
             vl[3 * m + a] = field();
+            if (!p->limiter) vl[3 * m + a] = ut[3 * m + a];   // unlimited: V = U~ (its field unused)
         }
     }
+    phis[M] = field();
     double* lcur = field();
     double* lprev = field();
     double* lpsin = field();
@@ -563,7 +570,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (int sg = L.segs - 1; sg >= 0; --sg) {
         const int s0 = sg * K;
         const int s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
-        // states psi^{s0} .. psi^{s1-1} of the segment
+        // states psi^{s0} .. psi^{s1-1} of the segment, from its checkpoint
+        // by the same steps as the forward sweep
         copy(seg[0], ckpt[sg]);
         for (int s = s0 + 1; s < s1; ++s)
             if (int rc = dispatch_step(p, seg[s - 1 - s0], seg[s - s0], cx, cy, cz, gm, step_ws, kStepFields * L.fb,
@@ -580,30 +588,28 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                 double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
                 S::k_antidiff<double><<<grd, blk, 0, st>>>(g, eps, phis[m - 1], prev[0], prev[1], prev[2], gm, U3[0],
                                                           U3[1], U3[2]);
-                for (int a = 0; a < 3; ++a) copy(V3[a], U3[a]);
                 if (p->limiter) {
                     A::k_bounds<<<grd, blk, 0, st>>>(g, psin, phis[m - 1], mx[m], mn[m], code[m]);
                     S::k_beta<double><<<grd, blk, 0, st>>>(g, eps, psin, phis[m - 1], U3[0], U3[1], U3[2], gm, bu[m],
                                                           bd[m]);
-                    S::k_limit<double><<<grd, blk, 0, st>>>(g, V3[0], V3[1], V3[2], bu[m], bd[m]);
+                    S::k_limit<double><<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], V3[0], V3[1], V3[2], bu[m],
+                                                           bd[m]);
                 }
                 S::k_donor<double><<<grd, blk, 0, st>>>(g, phis[m - 1], V3[0], V3[1], V3[2], gm, phis[m]);
             }
             if (int rc = launch_status("adjoint recompute")) return rc;
 
-            // reverse through the passes
-            fill0(lpsin);
-            for (int a = 0; a < 3; ++a) fill0(lv[a]);
+            // reverse through the passes.  No buffer is cleared: the first
+            // contribution each adjoint buffer receives in a step assigns it.
             for (int m = M; m >= 2; --m) {
                 const double* ph = phis[m - 1];
                 const double* prev[3];
                 for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : vl[3 * (m - 1) + a];
                 const double* U3[3] = {ut[3 * m], ut[3 * m + 1], ut[3 * m + 2]};
                 const double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
-                fill0(lprev);
-                if (m > 2)
-                    for (int a = 0; a < 3; ++a) fill0(lvp[a]);
-                A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1], lv[2]);
+                A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1], lv[2],
+                                                    1, m == M);
+                const double* lu3[3] = {lv[0], lv[1], lv[2]};   // unlimited: dJ/dU~ = dJ/dV
                 if (p->limiter) {
                     A::k_adj_limit<<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], bu[m], bd[m], lv[0], lv[1], lv[2],
                                                         lut[0], lut[1], lut[2], lbu, lbd);
@@ -611,19 +617,19 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                                                         lin, lout, lmx, lmn, lprev);
                     A::k_adj_beta2<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, lprev, lut[0], lut[1],
                                                         lut[2]);
-                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, code[m], lmx, lmn, lpsin, lprev);
-                } else {
-                    for (int a = 0; a < 3; ++a) copy(lut[a], lv[a]);
+                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, code[m], lmx, lmn, lpsin, lprev, m == M);
+                    for (int a = 0; a < 3; ++a) lu3[a] = lut[a];
                 }
                 double* tgt[3];
                 for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
-                A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lut[0], lut[1],
-                                                        lut[2], slots, slot_stride);
-                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
+                A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lu3[0], lu3[1],
+                                                        lu3[2], slots, slot_stride);
+                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2], m > 2);
                 std::swap(lcur, lprev);
                 for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
             }
-            A::k_adj_donor<<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, lcur, lpsin, dC[0], dC[1], dC[2]);
+            A::k_adj_donor<<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, lcur, lpsin, dC[0], dC[1], dC[2],
+                                                !(p->limiter && M >= 2), 0);
             std::swap(lcur, lpsin);
             if (int rc = launch_status("adjoint step")) return rc;
         }

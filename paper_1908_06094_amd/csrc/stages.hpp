@@ -218,20 +218,22 @@ __global__ void __launch_bounds__(256) k_beta(Geo g, double eps, const T* __rest
     bdn[c.q] = (T)((double)((pc - lo) * gc) / (out + eps));
 }
 
-// Limited velocities, in place over the antidiffusive ones.
+// Limited velocities from the antidiffusive ones (ul, vl, wl may be ut, vt,
+// wt themselves: each thread reads and writes only its own three faces).
 template <class T>
-__global__ void __launch_bounds__(256) k_limit(Geo g, T* __restrict__ ut, T* __restrict__ vt, T* __restrict__ wt,
+__global__ void __launch_bounds__(256) k_limit(Geo g, const T* ut, const T* vt, const T* wt, T* ul, T* vl, T* wl,
                                                const T* __restrict__ bup, const T* __restrict__ bdn)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
-    T* vel[3] = {ut, vt, wt};
+    const T* vel[3] = {ut, vt, wt};
+    T* lim[3] = {ul, vl, wl};
     const T up_c = bup[c.q], dn_c = bdn[c.q];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int R[3] = {c.i, c.j, c.k};
         if (closed(g, a) && R[a] == extent(g, a) - 1) {
-            vel[a][c.q] = T(0);
+            lim[a][c.q] = T(0);
             continue;
         }
         R[a] += 1;
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(256) k_limit(Geo g, T* __restrict__ ut, T* __r
         const T U = vel[a][c.q];
         const T up = min2(T(1), min2(dn_c, bup[qr]));
         const T dn = min2(T(1), min2(up_c, bdn[qr]));
-        vel[a][c.q] = (pos_part(U) * up) + (neg_part(U) * dn);
+        lim[a][c.q] = (pos_part(U) * up) + (neg_part(U) * dn);
     }
 }
 
