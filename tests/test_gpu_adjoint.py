@@ -38,6 +38,7 @@ def _say(msg):
     ((4, 7, 66), (C, P, C), 1, False, 3, 1),
     ((6, 13, 17), (P, C, P), 3, True, 4, 4),
     ((1, 3, 2), (P, P, P), 3, True, 2, 1),
+    ((5, 10, 24), (P, C, C), 3, False, 3, 2),
 ])
 def test_adjoint_matches_oracle(shape, bc, iters, lim, steps, k):
     torch = _torch()
