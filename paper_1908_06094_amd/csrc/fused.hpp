@@ -39,7 +39,8 @@
 // reciprocal with Newton refinement (div_nr, within an ulp of the IEEE
 // quotient).  In FP64 this changes results by a few ulp.  In FP32 (where the
 // product of three guarded denominators could underflow) the ratios are
-// taken one by one.
+// taken one by one, each from the hardware reciprocal (1 ulp), and the
+// update's quotient from the reciprocal with one residual correction.
 #pragma once
 
 #include "common.hpp"
@@ -119,7 +120,16 @@ __device__ __forceinline__ double div_nr(double n, double d)
     const double q = n * r;
     return __builtin_fma(r, __builtin_fma(-d, q, n), q);
 }
-__device__ __forceinline__ float div_nr(float n, float d) { return n / d; }
+// FP32 quotient from the hardware reciprocal (1 ulp) and one residual
+// correction: within an ulp of the IEEE quotient, without the scaling and
+// fix-up steps of the IEEE division sequence (every denominator is a normal
+// positive number).
+__device__ __forceinline__ float div_nr(float n, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = n * r;
+    return __builtin_fmaf(r, __builtin_fmaf(-d, q, n), q);
+}
 
 __device__ __forceinline__ double antidiff_face(double n0, double d0, double n1, double d1, double n2, double d2,
                                                 double vs1, double vs2, double gsum, double u)
@@ -136,10 +146,12 @@ __device__ __forceinline__ double antidiff_face(double n0, double d0, double n1,
 __device__ __forceinline__ float antidiff_face(float n0, float d0, float n1, float d1, float n2, float d2,
                                                float vs1, float vs2, float gsum, float u)
 {
-    const float A = __fdividef(n0, d0);
-    const float B1 = 0.5f * __fdividef(n1, d1);
-    const float B2 = 0.5f * __fdividef(n2, d2);
-    const float rgf = __fdividef(2.0f, gsum);      // 1 / Gf
+    // the ratios from hardware reciprocals (1 ulp each; an IEEE division is
+    // about ten instructions)
+    const float A = n0 * __builtin_amdgcn_rcpf(d0);
+    const float B1 = 0.5f * (n1 * __builtin_amdgcn_rcpf(d1));
+    const float B2 = 0.5f * (n2 * __builtin_amdgcn_rcpf(d2));
+    const float rgf = 2.0f * __builtin_amdgcn_rcpf(gsum);      // 1 / Gf
     const float au = u < 0.0f ? -u : u;
     return (au - (u * u) * rgf) * A - (u * rgf) * ((0.25f * vs1) * B1 + (0.25f * vs2) * B2);
 }
