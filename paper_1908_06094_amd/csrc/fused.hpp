@@ -105,18 +105,17 @@ __device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_
 //   vs1/vs2 the sums of the four transverse face velocities (Vb = vs / 4)
 //   gsum    G(left) + G(right) (Gf = gsum / 2), u the face velocity
 // ---------------------------------------------------------------------------
-// FP64 quotient from the hardware reciprocal refined by two Newton steps and
-// one residual correction (Markstein's scheme): within an ulp of the IEEE
-// quotient, without the scaling and special-case steps of the IEEE division
-// sequence.  Every denominator here is a normal positive number (pair sums
-// guarded by eps, products of them, G).
+// FP64 quotient from the hardware reciprocal refined by one Newton step and
+// one residual correction on the quotient (Markstein's scheme): the Newton
+// step squares the reciprocal's relative error, the correction squares the
+// quotient's again, which leaves the rounding of the last step: within an
+// ulp of the IEEE quotient, without the scaling and special-case steps of
+// the IEEE division sequence.  Every denominator here is a normal positive
+// number (pair sums guarded by eps, products of them, G).
 __device__ __forceinline__ double div_nr(double n, double d)
 {
     double r = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
     const double q = n * r;
     return __builtin_fma(r, __builtin_fma(-d, q, n), q);
 }
