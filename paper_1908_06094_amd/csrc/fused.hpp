@@ -136,7 +136,7 @@ __device__ __forceinline__ double antidiff_face(double n0, double d0, double n1,
     // (|u| - u^2/Gf) n0/d0 - (u/Gf)((vs1/4)(n1/(2 d1)) + (vs2/4)(n2/(2 d2)))
     //   = [(|u| gsum - 2u^2) n0 d1 d2 - (u/4) d0 (vs1 n1 d2 + vs2 n2 d1)] / (gsum d0 d1 d2)
     const double d12 = d1 * d2;
-    const double au = u < 0.0 ? -u : u;
+    const double au = __builtin_fabs(u);   // |u| (+0 for u = -0: only the sign of a zero can differ)
     const double t1 = ((au * gsum - 2.0 * (u * u)) * n0) * d12;
     const double t2 = (0.25 * u) * d0 * (vs1 * n1 * d2 + vs2 * n2 * d1);
     return div_nr(t1 - t2, (gsum * d0) * d12);
@@ -151,7 +151,7 @@ __device__ __forceinline__ float antidiff_face(float n0, float d0, float n1, flo
     const float B1 = 0.5f * (n1 * __builtin_amdgcn_rcpf(d1));
     const float B2 = 0.5f * (n2 * __builtin_amdgcn_rcpf(d2));
     const float rgf = 2.0f * __builtin_amdgcn_rcpf(gsum);      // 1 / Gf
-    const float au = u < 0.0f ? -u : u;
+    const float au = __builtin_fabsf(u);
     return (au - (u * u) * rgf) * A - (u * rgf) * ((0.25f * vs1) * B1 + (0.25f * vs2) * B2);
 }
 
