@@ -57,6 +57,18 @@ __device__ __forceinline__ double sgn(double c) { return c > 0.0 ? 1.0 : (c < 0.
 __device__ __forceinline__ double ppos(double c) { return c > 0.0 ? c : 0.0; }
 __device__ __forceinline__ double pneg(double c) { return c < 0.0 ? c : 0.0; }
 
+// 1/d from the hardware reciprocal refined by two Newton steps (within an
+// ulp of the correctly rounded reciprocal; d is a normal positive number).
+// A kernel that divides several values by the same denominator multiplies
+// by this instead (an IEEE FP64 division is about ten instructions); the
+// partial derivatives then differ from the quotients' by a few ulp.
+__device__ __forceinline__ double rcp_nr(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+}
+
 // Index (0, 1, 2) of the first minimal entry of (1, x, y).
 __device__ __forceinline__ int first_min3(double x, double y)
 {
@@ -240,6 +252,41 @@ __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* 
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
+    // Fast path: every axis periodic with >= 3 cells, or c >= 1 away from a
+    // closed end.  Then the seven cells whose cross contains c are distinct,
+    // and candidate y = c + step(m) reaches c only through its entry
+    // opposite to m (the same candidates, order and sums as below).
+    bool fast = true;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int n = extent(g, b), cb = b == 0 ? c.i : (b == 1 ? c.j : c.k);
+        fast = fast && (closed(g, b) ? (cb >= 1 && cb <= n - 2) : n >= 3);
+    }
+    if (fast) {
+        const long long st[3] = {1, g.sy, g.sz};
+        const int cc[3] = {c.i, c.j, c.k};
+        double gp = 0.0, gf = 0.0;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            long long yq = c.q;
+            int want = 0;   // the entry of y that is c
+            if (m > 0) {
+                const int b = (m - 1) >> 1, s = (m & 1) ? -1 : 1;   // m = 1, 3, 5: the lower neighbour
+                const int n = extent(g, b);
+                int v = cc[b] + s;
+                v = v < 0 ? v + n : (v >= n ? v - n : v);
+                yq += (long long)(v - cc[b]) * st[b];
+                want = (m & 1) ? m + 1 : m - 1;
+            }
+            const int am = code[2 * yq], an = code[2 * yq + 1];
+            if (am % 7 == want) (am < 7 ? gp : gf) += lmx[yq];
+            if (an % 7 == want) (an < 7 ? gp : gf) += lmn[yq];
+        }
+        if (assign_psin) lpsin[c.q] = gp;
+        else lpsin[c.q] += gp;
+        lphi[c.q] += gf;
+        return;
+    }
     // the cells whose cross contains c (the cross is symmetric)
     const Pt cand[7] = {mapped(g, c.i, c.j, c.k),     mapped(g, c.i - 1, c.j, c.k), mapped(g, c.i + 1, c.j, c.k),
                         mapped(g, c.i, c.j - 1, c.k), mapped(g, c.i, c.j + 1, c.k), mapped(g, c.i, c.j, c.k - 1),
@@ -303,16 +350,16 @@ __global__ void __launch_bounds__(256) k_adj_beta1(Geo g, double eps, const doub
     const double* U3[3] = {ut, vt, wt};
     double in, out;
     in_out(g, c, phi, U3, in, out);
-    const double din = in + eps, dout = out + eps;
+    const double rin = rcp_nr(in + eps), rout = rcp_nr(out + eps);
     const double G = gm[c.q], pc = phi[c.q];
-    const double bu = ((mx[c.q] - pc) * G) / din;
-    const double bd = ((pc - mn[c.q]) * G) / dout;
+    const double bu = ((mx[c.q] - pc) * G) * rin;
+    const double bd = ((pc - mn[c.q]) * G) * rout;
     const double gu = lbup[c.q], gd = lbdn[c.q];
-    lmx[c.q] = gu * G / din;
-    lmn[c.q] = -(gd * G / dout);
-    lphi[c.q] += -gu * G / din + gd * G / dout;
-    lin[c.q] = -gu * bu / din;
-    lout[c.q] = -gd * bd / dout;
+    lmx[c.q] = gu * G * rin;
+    lmn[c.q] = -(gd * G * rout);
+    lphi[c.q] += -gu * G * rin + gd * G * rout;
+    lin[c.q] = -gu * bu * rin;
+    lout[c.q] = -gd * bd * rout;
 }
 
 // in(c)  = sum_a [U(c-1/2)]+ phi(c-1) - [U(c+1/2)]- phi(c+1)
@@ -392,8 +439,9 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
         const double lam = lam3[a][c.q];
         const double pL = phi[c.q], pR = phi[at(g, R[0], R[1], R[2])];
         const double D0 = (pR + pL) + eps;
-        const double A = (pR - pL) / D0;
-        double B[2], Vb[2], Dt[2], Sp[2], Sm[2];
+        const double rD0 = rcp_nr(D0);
+        const double A = (pR - pL) * rD0;
+        double B[2], Vb[2], rDt[2], Sp[2], Sm[2];
         int sidx = 0;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -403,8 +451,8 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
             Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
             Sp[sidx] = phi[at(g, Rp[0], Rp[1], Rp[2])] + phi[at(g, Lp[0], Lp[1], Lp[2])];
             Sm[sidx] = phi[at(g, Rm[0], Rm[1], Rm[2])] + phi[at(g, Lm[0], Lm[1], Lm[2])];
-            Dt[sidx] = (Sp[sidx] + Sm[sidx]) + eps;
-            B[sidx] = 0.5 * ((Sp[sidx] - Sm[sidx]) / Dt[sidx]);
+            rDt[sidx] = rcp_nr((Sp[sidx] + Sm[sidx]) + eps);
+            B[sidx] = 0.5 * ((Sp[sidx] - Sm[sidx]) * rDt[sidx]);
             const long long f0 = face_idx(g, t, c.i, c.j, c.k), f1 = face_idx(g, t, R[0], R[1], R[2]);
             const long long f2 = face_idx(g, t, Lm[0], Lm[1], Lm[2]), f3 = face_idx(g, t, Rm[0], Rm[1], Rm[2]);
             const double* vt = vel[t];
@@ -413,20 +461,22 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
             Vb[sidx] = 0.25 * ((v0 + v1) + (v2 + v3));
             ++sidx;
         }
-        const double Gf = 0.5 * (gm[c.q] + gm[at(g, R[0], R[1], R[2])]);
+        const double rGf = rcp_nr(0.5 * (gm[c.q] + gm[at(g, R[0], R[1], R[2])]));
         const double U = vel[a] ? vel[a][fo] : 0.0;
         const double S = (Vb[0] * B[0]) + (Vb[1] * B[1]);
-        const double dU = (sgn(U) - 2.0 * U / Gf) * A - S / Gf;
-        const double dA = (U < 0.0 ? -U : U) - (U * U) / Gf;
-        const double dS = -U / Gf;
+        const double dU = (sgn(U) - 2.0 * U * rGf) * A - S * rGf;
+        const double dA = (U < 0.0 ? -U : U) - (U * U) * rGf;
+        const double dS = -U * rGf;
         const double gA = lam * dA;
-        s[0 * field] = gA * (2.0 * pL + eps) / (D0 * D0);
-        s[1 * field] = -(gA * (2.0 * pR + eps) / (D0 * D0));
+        const double r2 = rD0 * rD0;
+        s[0 * field] = gA * (2.0 * pL + eps) * r2;
+        s[1 * field] = -(gA * (2.0 * pR + eps) * r2);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double gB = lam * dS * Vb[q];
-            s[(2 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) / (Dt[q] * Dt[q]));
-            s[(3 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) / (Dt[q] * Dt[q]));
+            const double rt2 = rDt[q] * rDt[q];
+            s[(2 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) * rt2);
+            s[(3 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
             s[(6 + q) * field] = 0.25 * (lam * dS * B[q]);
         }
         s[8 * field] = lam * dU;
