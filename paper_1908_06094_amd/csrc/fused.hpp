@@ -43,6 +43,8 @@
 // update's quotient from the reciprocal with one residual correction.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace mpdata {
@@ -369,7 +371,13 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
 
         // March step t: plane t (bank N) has arrived; velocities and beta of
         // plane k = t-1 (bank C) are formed, and plane k-1 (bank P) is updated.
-        auto step = [&](const int t, Bank<T>& P, Bank<T>& C, Bank<T>& N) __attribute__((always_inline)) {
+        // Step modes.  The first two steps of a segment only prime the
+        // banks: plane kb-2 (loads, LDS slots, pair sums) and plane kb-1 (the
+        // same, plus the z-face velocity above plane kb-2, which plane kb-1's
+        // beta reads); from plane kb on, every stage runs.
+        constexpr int kPrimeLoad = 0, kPrimeUz = 1, kFull = 2;
+        auto step = [&](const int t, Bank<T>& P, Bank<T>& C, Bank<T>& N, auto mode_tag) __attribute__((always_inline)) {
+            constexpr int kMode = decltype(mode_tag)::value;
             // the prefetch of plane t and the previous step's stores, both
             // issued one step ago, have landed: every later wait is free
             vmem_wait_all();
@@ -412,7 +420,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             const T nphi_c = lane_next(C.phi);
 
             T ux = zero, uy = zero, uz = zero;
-            if (do_uxz) {
+            if (do_uxz && kMode != kPrimeLoad) {
                 const T px_c_up = S.px[sc][up][lane];
                 const T px_c_dn = S.px[sc][dn][lane];
                 const T vpxdn_c = S.vpx[sc][dn][lane];
@@ -421,16 +429,24 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                 const T vpz_dn = S.vpz[dn][lane];
                 const T gx_c = C.g + lane_next(C.g);
                 // x face (i+1/2, j, k): transverse y then z
-                ux = antidiff_face(nphi_c - C.phi, C.px + eps,
-                                   px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
-                                   N.px - P.px, (N.px + P.px) + eps,
-                                   C.vpx + vpxdn_c, wsx, gx_c, C.u);
+                if (kMode == kFull)
+                    ux = antidiff_face(nphi_c - C.phi, C.px + eps,
+                                       px_c_up - px_c_dn, (px_c_up + px_c_dn) + eps,
+                                       N.px - P.px, (N.px + P.px) + eps,
+                                       C.vpx + vpxdn_c, wsx, gx_c, C.u);
                 // z face (i, j, k+1/2): transverse x then y
                 const T pz_nx = lane_next(pz_c), pz_pv = lane_prev(pz_c);
                 uz = antidiff_face(N.phi - C.phi, pz_c + eps,
                                    pz_nx - pz_pv, (pz_nx + pz_pv) + eps,
                                    pz_up - pz_dn, (pz_up + pz_dn) + eps,
                                    upz_c + lane_prev(upz_c), vpz_c + vpz_dn, C.g + N.g, C.w);
+            }
+            if (kMode != kFull) {
+                if (kMode == kPrimeUz && do_uxz) uz_p = uz;
+                wsx = N.wpx + C.wpx;
+                wsy = N.wpy + C.wpy;
+                lds_barrier();   // the next step rewrites the slots read above
+                return;
             }
             if (do_uy) {
                 // y face (i, j+1/2, k): transverse x then z
@@ -526,9 +542,15 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                                          // phase-2 and phase-3 barriers already separate them
         };
 
-        load(kb - 3, R);
-        for (int t = kb - 3; t <= t_last; ++t) {
-            step(t, B0, B1, B2);
+        load(kb - 2, R);
+        step(kb - 2, B0, B1, B2, std::integral_constant<int, kPrimeLoad>{});
+        B0 = B1;
+        B1 = B2;
+        step(kb - 1, B0, B1, B2, std::integral_constant<int, kPrimeUz>{});
+        B0 = B1;
+        B1 = B2;
+        for (int t = kb; t <= t_last; ++t) {
+            step(t, B0, B1, B2, std::integral_constant<int, kFull>{});
             B0 = B1;
             B1 = B2;
         }
