@@ -65,6 +65,8 @@ CASES = [
     ((12, 5, 3), (P, C, P), 3, True),
     ((1, 1, 1), (P, P, P), 2, True),
     ((4, 1, 200), (P, C, C), 3, True),
+    ((2, 17, 70), (P, C, C), 3, True),     # segments prime from levels below the bottom (clamped)
+    ((2, 9, 40), (P, P, P), 2, True),      # ... and wrapped
 ]
 
 
@@ -209,7 +211,7 @@ TOL32 = 3e-5
 
 
 @pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6], CASES[8],
-                                                CASES[10]])
+                                                CASES[10], CASES[11], CASES[12]])
 def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
     torch = _torch()
     mp = _mp()
