@@ -96,7 +96,10 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
  * returns dJ/dpsi0 and dJ/d(cx, cy, cz) (dJ_dcz may be NULL to skip it; the
  * closed-wall slots of the gradients are 0).  The forward trajectory is
  * recomputed from psi0: states are kept every checkpoint_every steps (0 =
- * only psi0) and each segment is recomputed before its reverse sweep.  At
+ * only psi0) and each segment is recomputed before its reverse sweep, its
+ * steps storing the intermediates the reverse sweep reads (the forward
+ * sweep runs the same kernels, so the result does not depend on
+ * checkpoint_every; psiT_out agrees with mpdata_run to rounding).  At
  * the kinks of max/min the derivative follows the branch the forward step
  * took ([c]+ differentiates to [c > 0], 1/2 at c = 0, |c| to sign(c) with sign(0) = 0,
  * min(1, min(a, b)) to its first minimal entry, the limiter bounds to their

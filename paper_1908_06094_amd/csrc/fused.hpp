@@ -211,6 +211,16 @@ struct PassArgs {
     double eps;
     int tiles_x, tiles_y;
     int vel_tiled;   // u, v, w are in the tile layout (passes >= 3), else (nz, ny, nx)
+    // What the recording kernels (REC, FP64, for the adjoint) also store, as
+    // (nz, ny, nx) fields: the antidiffusive velocities and (with the
+    // limiter) beta, clamped to at most 1 (min(1, beta) is all that the
+    // limited velocities and their adjoint's branch choices read, and beta
+    // only matters where it is below 1).
+    T* rux;
+    T* ruy;
+    T* ruz;
+    T* rbu;
+    T* rbd;
 };
 
 // Tile layout of the limited velocities that one pass hands to the next
@@ -285,7 +295,7 @@ struct Raw {
 //   ROLE 2: the outer halo rows (0 and R-1): their loads and LDS slots and,
 //           with the limiter, (row 0) the y-face velocity below row 1,
 //           which row 1's beta needs.
-template <class T, bool LIMIT, bool WRITE_VEL, int ROLE>
+template <class T, bool LIMIT, bool WRITE_VEL, int ROLE, bool REC>
 __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
                                           const int kb, const int ke)
 {
@@ -457,6 +467,17 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                                    C.upy + lane_prev(C.upy), wsy, C.gpy, C.v);
             }
 
+            // recording: the antidiffusive velocities of plane k (stored at
+            // once: these stores follow this step's prefetch)
+            const int kc = t - 1;
+            const bool rec_here = REC && writer && kc >= kb && kc < ke;
+            const long long qc = (long long)kc * geo.sz + col;
+            if (REC && rec_here) {
+                a.rux[qc] = ux;
+                a.ruy[qc] = uy;
+                a.ruz[qc] = uz;
+            }
+
             // limited velocities: x, y at plane k; z at face k-1/2
             T ulx = ux, uly = uy, ulz = uz_p;
             if (LIMIT) {
@@ -496,6 +517,10 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                     }
                     S.bup[row][lane] = bup;
                     S.bdn[row][lane] = bdn;
+                    if (REC && rec_here) {
+                        a.rbu[qc] = bup;
+                        a.rbd[qc] = bdn;
+                    }
                 }
                 auto lim = [](T x, T y) __attribute__((always_inline)) {
                     return sizeof(T) == 8 ? fmn(x, y) : min3(T(1), x, y);
@@ -563,24 +588,24 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
 // several rows takes the role of the row that needs most).  FP32 runs every
 // wave in role 0: there only two waves of twelve hold no output row, and
 // the kernel with three loop bodies spills more of its 80 registers.
-template <class T, bool LIMIT, bool WRITE_VEL>
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
 __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
                                              const int kb, const int ke)
 {
     constexpr int kRows = Tile<T>::rows, kRowsPerWave = 64 / Tile<T>::lanes;
     static_assert(kHalo == 2, "the row roles assume a halo of 2");
     if (sizeof(T) == 4) {
-        pass_rows<T, LIMIT, WRITE_VEL, 0>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 0, REC>(geo, a, S, tile, kb, ke);
         return;
     }
     const int r_lo = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) * kRowsPerWave);
     const int r_hi = r_lo + kRowsPerWave - 1;
     if (r_lo <= kRows - 3 && r_hi >= 2)
-        pass_rows<T, LIMIT, WRITE_VEL, 0>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 0, REC>(geo, a, S, tile, kb, ke);
     else if (r_lo <= kRows - 2 && r_hi >= 1)
-        pass_rows<T, LIMIT, WRITE_VEL, 1>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 1, REC>(geo, a, S, tile, kb, ke);
     else
-        pass_rows<T, LIMIT, WRITE_VEL, 2>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 2, REC>(geo, a, S, tile, kb, ke);
 }
 
 // Logical workgroup id: the dispatcher deals workgroups round-robin over the
@@ -595,7 +620,7 @@ __device__ __forceinline__ int xcd_grouped_id()
 // pairs in tile-major order are cut into equal contiguous ranges, one per
 // workgroup, so every workgroup marches the same number of planes (a range
 // may span a tile boundary).
-template <class T, bool LIMIT, bool WRITE_VEL>
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
 __global__ void __launch_bounds__(kThreads, Tile<T>::waves_per_simd) k_pass(Geo geo, PassArgs<T> a)
 {
     __shared__ Slots<T> S;
@@ -610,7 +635,7 @@ __global__ void __launch_bounds__(kThreads, Tile<T>::waves_per_simd) k_pass(Geo 
         const int kb = (int)(w0 - (long long)tile * geo.nz);
         const int ke = (int)((long long)kb + (w1 - w0) < geo.nz ? kb + (w1 - w0) : geo.nz);
         w0 += ke - kb;
-        pass_segment<T, LIMIT, WRITE_VEL>(geo, a, S, tile, kb, ke);
+        pass_segment<T, LIMIT, WRITE_VEL, REC>(geo, a, S, tile, kb, ke);
     }
 }
 

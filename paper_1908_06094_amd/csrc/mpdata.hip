@@ -295,14 +295,14 @@ int pass_grid(long long total_planes)
     return n < 8 ? 8 : (int)n;
 }
 
-template <class T, bool LIMIT, bool WRITE_VEL>
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
 int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hipStream_t st)
 {
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
     Timed tm(MPDATA_KERNEL_PASS, st);
     const int grid = pass_grid(total) * mpdata::fused::Tile<T>::wgs_per_cu;
-    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
+    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
     return launch_status("fused corrective pass");
 }
 
@@ -465,14 +465,65 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     L.K = K;
     L.segs = nsteps > 0 ? (nsteps + K - 1) / K : 1;
     L.M = p->iters;
-    // checkpoints + segment states + per corrective pass the step's recomputed
-    // intermediates (the pass's input iterate, U~ x3, V x3, beta x2, mx, mn,
-    // extremal-entry codes) + the step's output + 18 adjoint fields (cur,
-    // prev, psin, V x3, Vprev x3, U~ x3, beta x2, lin, lout, lmx, lmn) +
-    // antidiffusive slots (27) + a forward step's workspace + a zero field
-    // and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)12 * (L.M - 1) + 1 + 18 + 27 + kStepFields + 2;
+    // checkpoints + segment states + for each step of a segment and each
+    // corrective pass a record (the pass's input iterate, U~ x3, V x3, beta
+    // x2) + the bounds of the step being reversed (mx, mn, extremal-entry
+    // codes per pass) + a sink for the segment's last output + 18 adjoint
+    // fields (cur, prev, psin, V x3, Vprev x3, U~ x3, beta x2, lin, lout,
+    // lmx, lmn) + antidiffusive slots (27) + a zero field and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 18 + 27 + 2;
     return L;
+}
+
+// The intermediates of one forward step that its adjoint reads, per
+// corrective pass m = 2..M: phis[m - 1] (the pass's input iterate), ut / vl
+// [3 m + axis] (its antidiffusive and limited velocities), bu / bd [m]
+// (beta, at most 1).
+struct AdjRec {
+    std::vector<double*> phis, ut, vl, bu, bd;
+};
+
+// One forward step through the recording kernels (the donor-cell pass, then
+// the fused corrective passes that also store their antidiffusive
+// velocities and beta), keeping the step's intermediates in R.  The
+// adjoint's forward sweep and its segment recomputations both take this
+// path, so a state is the same whatever the checkpoint interval.
+int step_record(const mpdata_problem* p, const double* psin, double* psout, const double* cx, const double* cy,
+                const double* cz, const double* gm, const AdjRec& R, hipStream_t st)
+{
+    namespace F = mpdata::fused;
+    const int M = p->iters;
+    mpdata::Geo g = geo_of(p);
+    dim3 blk(64, 4, 1);
+    dim3 dgrd((p->nx + 63) / 64, (p->ny + 3) / 4, (p->nz + F::kDonorChunk - 1) / F::kDonorChunk);
+    F::k_donor_march<double><<<dgrd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, M == 1 ? psout : R.phis[1]);
+    if (int rc = launch_status("adjoint: donor-cell pass")) return rc;
+    F::PassArgs<double> a{};
+    a.psin = psin;
+    a.g = gm;
+    a.eps = p->eps > 0.0 ? p->eps : 1e-15;
+    a.tiles_x = (p->nx + F::Tile<double>::tile_x - 1) / F::Tile<double>::tile_x;
+    a.tiles_y = (p->ny + F::Tile<double>::tile_y - 1) / F::Tile<double>::tile_y;
+    a.vel_tiled = 0;
+    for (int m = 2; m <= M; ++m) {
+        a.phi = R.phis[m - 1];
+        a.out = m == M ? psout : R.phis[m];
+        a.u = m == 2 ? cx : R.vl[3 * (m - 1)];
+        a.v = m == 2 ? cy : R.vl[3 * (m - 1) + 1];
+        a.w = m == 2 ? cz : R.vl[3 * (m - 1) + 2];
+        a.ul = R.vl[3 * m];
+        a.vl = R.vl[3 * m + 1];
+        a.wl = R.vl[3 * m + 2];
+        a.rux = R.ut[3 * m];
+        a.ruy = R.ut[3 * m + 1];
+        a.ruz = R.ut[3 * m + 2];
+        a.rbu = R.bu[m];
+        a.rbd = R.bd[m];
+        const int rc = p->limiter ? launch_pass<double, true, true, true>(p, a, st)
+                                  : launch_pass<double, false, true, true>(p, a, st);
+        if (rc) return rc;
+    }
+    return MPDATA_OK;
 }
 
 int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, const double* cx, const double* cy,
@@ -480,7 +531,6 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                 double* dcz, double* psiT, void* ws, hipStream_t st)
 {
     namespace A = mpdata::adj;
-    namespace S = mpdata::stages;
     const AdjLayout L = adj_layout(p, nsteps, K);
     const long long n = L.n;
     char* base = (char*)ws;
@@ -490,25 +540,32 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (auto& f : ckpt) f = field();
     for (auto& f : seg) f = field();
     const int M = L.M;
-    // the intermediates of the step being reversed, pass m = 2..M (phis[m -
-    // 1] is the pass's input iterate, phis[M] the step's output)
-    std::vector<double*> phis(M + 1, nullptr), ut(3 * (M + 1), nullptr), vl(3 * (M + 1), nullptr),
-        bu(M + 1, nullptr), bd(M + 1, nullptr), mx(M + 1, nullptr), mn(M + 1, nullptr);
+    // per-step records of a segment, and the bounds of the step being reversed
+    std::vector<AdjRec> rec(K);
+    for (AdjRec& R : rec) {
+        R.phis.assign(M + 1, nullptr);
+        R.ut.assign(3 * (M + 1), nullptr);
+        R.vl.assign(3 * (M + 1), nullptr);
+        R.bu.assign(M + 1, nullptr);
+        R.bd.assign(M + 1, nullptr);
+        for (int m = 2; m <= M; ++m) {
+            R.phis[m - 1] = field();
+            R.bu[m] = field();
+            R.bd[m] = field();
+            for (int a = 0; a < 3; ++a) {
+                R.ut[3 * m + a] = field();
+                R.vl[3 * m + a] = field();
+            }
+        }
+    }
+    std::vector<double*> mx(M + 1, nullptr), mn(M + 1, nullptr);
     std::vector<unsigned char*> code(M + 1, nullptr);   // 2 bytes per cell in a field of 8
     for (int m = 2; m <= M; ++m) {
-        phis[m - 1] = field();
-        bu[m] = field();
-        bd[m] = field();
         mx[m] = field();
         mn[m] = field();
         code[m] = (unsigned char*)field();
-        for (int a = 0; a < 3; ++a) {
-            ut[3 * m + a] = field();
-            vl[3 * m + a] = field();
-            if (!p->limiter) vl[3 * m + a] = ut[3 * m + a];   // unlimited: V = U~ (its field unused)
-        }
     }
-    phis[M] = field();
+    double* sink = field();
     double* lcur = field();
     double* lprev = field();
     double* lpsin = field();
@@ -523,8 +580,6 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     double* lmn = field();
     double* slots = field();
     next += 26;                       // the 27 slot fields are contiguous
-    void* step_ws = base + L.fb * next;
-    next += kStepFields;
     double* zero_w = field();
     double* dcz_scratch = field();
     const long long slot_stride = (long long)(L.fb / sizeof(double));
@@ -559,7 +614,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (int s = 0; s < nsteps; ++s) {
         const bool store = (s + 1) % K == 0 && (s + 1) / K < L.segs;
         double* dst = store ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
-        if (int rc = dispatch_step(p, cur, dst, cx, cy, cz, gm, step_ws, kStepFields * L.fb, st)) return rc;
+        if (int rc = step_record(p, cur, dst, cx, cy, cz, gm, rec[0], st)) return rc;   // records unused here
         cur = dst;
     }
     if (psiT && cur != psiT) copy(psiT, cur);
@@ -570,49 +625,35 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (int sg = L.segs - 1; sg >= 0; --sg) {
         const int s0 = sg * K;
         const int s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
-        // states psi^{s0} .. psi^{s1-1} of the segment, from its checkpoint
-        // by the same steps as the forward sweep
+        // the segment's steps again from its checkpoint, by the same kernels
+        // as the forward sweep, keeping each step's intermediates
         copy(seg[0], ckpt[sg]);
-        for (int s = s0 + 1; s < s1; ++s)
-            if (int rc = dispatch_step(p, seg[s - 1 - s0], seg[s - s0], cx, cy, cz, gm, step_ws, kStepFields * L.fb,
-                                       st))
+        for (int r = 0; r < s1 - s0; ++r)
+            if (int rc = step_record(p, seg[r], r + 1 < s1 - s0 ? seg[r + 1] : sink, cx, cy, cz, gm, rec[r], st))
                 return rc;
-        for (int s = s1 - 1; s >= s0; --s) {
-            const double* psin = seg[s - s0];
-            // the step's intermediates, stage by stage
-            S::k_donor<double><<<grd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, phis[1]);
-            for (int m = 2; m <= M; ++m) {
-                const double* prev[3];
-                for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : vl[3 * (m - 1) + a];
-                double* U3[3] = {ut[3 * m], ut[3 * m + 1], ut[3 * m + 2]};
-                double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
-                S::k_antidiff<double><<<grd, blk, 0, st>>>(g, eps, phis[m - 1], prev[0], prev[1], prev[2], gm, U3[0],
-                                                          U3[1], U3[2]);
-                if (p->limiter) {
-                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, phis[m - 1], mx[m], mn[m], code[m]);
-                    S::k_beta<double><<<grd, blk, 0, st>>>(g, eps, psin, phis[m - 1], U3[0], U3[1], U3[2], gm, bu[m],
-                                                          bd[m]);
-                    S::k_limit<double><<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], V3[0], V3[1], V3[2], bu[m],
-                                                           bd[m]);
-                }
-                S::k_donor<double><<<grd, blk, 0, st>>>(g, phis[m - 1], V3[0], V3[1], V3[2], gm, phis[m]);
-            }
-            if (int rc = launch_status("adjoint recompute")) return rc;
+        for (int r = s1 - s0 - 1; r >= 0; --r) {
+            const AdjRec& R = rec[r];
+            const double* psin = seg[r];
+            // the step's bounds and the first extremal entries they came from
+            if (p->limiter)
+                for (int m = 2; m <= M; ++m)
+                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, R.phis[m - 1], mx[m], mn[m], code[m]);
+            if (int rc = launch_status("adjoint bounds")) return rc;
 
             // reverse through the passes.  No buffer is cleared: the first
             // contribution each adjoint buffer receives in a step assigns it.
             for (int m = M; m >= 2; --m) {
-                const double* ph = phis[m - 1];
+                const double* ph = R.phis[m - 1];
                 const double* prev[3];
-                for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : vl[3 * (m - 1) + a];
-                const double* U3[3] = {ut[3 * m], ut[3 * m + 1], ut[3 * m + 2]};
-                const double* V3[3] = {vl[3 * m], vl[3 * m + 1], vl[3 * m + 2]};
+                for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : R.vl[3 * (m - 1) + a];
+                const double* U3[3] = {R.ut[3 * m], R.ut[3 * m + 1], R.ut[3 * m + 2]};
+                const double* V3[3] = {R.vl[3 * m], R.vl[3 * m + 1], R.vl[3 * m + 2]};
                 A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1], lv[2],
                                                     1, m == M);
                 const double* lu3[3] = {lv[0], lv[1], lv[2]};   // unlimited: dJ/dU~ = dJ/dV
                 if (p->limiter) {
-                    A::k_adj_limit<<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], bu[m], bd[m], lv[0], lv[1], lv[2],
-                                                        lut[0], lut[1], lut[2], lbu, lbd);
+                    A::k_adj_limit<<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], R.bu[m], R.bd[m], lv[0], lv[1],
+                                                        lv[2], lut[0], lut[1], lut[2], lbu, lbd);
                     A::k_adj_beta1<<<grd, blk, 0, st>>>(g, eps, ph, U3[0], U3[1], U3[2], mx[m], mn[m], gm, lbu, lbd,
                                                         lin, lout, lmx, lmn, lprev);
                     A::k_adj_beta2<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, lprev, lut[0], lut[1],
