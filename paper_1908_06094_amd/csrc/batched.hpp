@@ -156,7 +156,7 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
             d.tracers = it.ntracers;
             tb.donor[par].push_back(d);
             for (int m = 2; m <= M; ++m) {
-                BatchEntry<T> e;
+                BatchEntry<T> e{};
                 e.geo = g;
                 PassArgs<T>& a = e.args;
                 a.phi = P.f[(m - 2) & 1];               // X_{m-1}: X0, X1, X0, ...

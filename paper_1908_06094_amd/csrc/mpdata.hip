@@ -322,7 +322,7 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     }
     if (int rc = launch_status("donor-cell pass")) return rc;
 
-    mpdata::fused::PassArgs<T> a;
+    mpdata::fused::PassArgs<T> a{};
     a.psin = psin;
     a.g = gm;
     a.eps = p->eps > 0.0 ? p->eps : 1e-15;
