@@ -37,13 +37,13 @@ def make_workload(name, dtype):
     import workloads
 
     if name == "latlon-1024x512x80":
-        w = workloads.config3()
+        w = workloads.latlon_wave()
         if dtype == "f32":
-            w = workloads.config3_fp32_inputs(w)
+            w = workloads.rounded_to_fp32(w)
     elif name == "latlon-256x128x60":
-        w = workloads.config2()
+        w = workloads.latlon_solid_body()
     elif name == "2d-64x64":
-        w = workloads.config1()
+        w = workloads.gaussian_2d()
     else:
         raise SystemExit(f"unknown workload {name}")
     return w
@@ -108,8 +108,8 @@ def time_adjoint(mp, torch, dev, steps=20, checkpoint_every=5, reps=3):
 
     import workloads
 
-    w = workloads.config2()
-    wt = torch.from_numpy(workloads.config5_weights(w.shape)).to(dev)
+    w = workloads.latlon_solid_body()
+    wt = torch.from_numpy(workloads.cost_weights(w.shape)).to(dev)
     psi0, cx, cy, cz, g = (torch.from_numpy(a).to(dev) for a in (w.psi, w.cx, w.cy, w.cz, w.g))
     kw = dict(iters=2, limiter=True, bc=w.bc)
     out = psi0.clone()
@@ -143,7 +143,7 @@ def time_batched(mp, torch, dev, steps=20, reps=3):
 
     import workloads
 
-    probs_h = workloads.config4()
+    probs_h = workloads.batched_problems()
     probs = [{k: torch.from_numpy(v).to(dev) for k, v in p.items()} for p in probs_h]
     del probs_h
     start = [p["psi"].clone() for p in probs]

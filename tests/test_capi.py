@@ -44,7 +44,7 @@ def _no_device():
     they are only made where no GPU could ever be reached."""
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
-        pytest.skip("host-only argument checks (no device calls with bogus pointers on a GPU box)")
+        pytest.skip("host-only argument checks (no device calls with bogus pointers where a GPU is present)")
 
 
 def _call_step(mp, p, psi_in=8, psi_out=16, ws_bytes=None, ws=256):

@@ -94,18 +94,18 @@ def test_autograd_function_matches_adjoint():
         assert torch.allclose(x.grad, r, rtol=0, atol=0)
 
 
-def test_config5_grid_matches_oracle_reverse_sweep():
+def test_adjoint_256x128x60_matches_oracle_reverse_sweep():
     """The exact check at scale: on the full 256x128x60 lat-lon grid (solid-body
     winds, limiter, 2 passes) the GPU adjoint over 3 steps with checkpoints
     every 2 equals the oracle's reverse sweep to 1e-11."""
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    w0 = workloads.config2()
+    w0 = workloads.latlon_solid_body()
     steps = 3
     p = oracle.RefProblem(w0.shape[2], w0.shape[1], w0.shape[0], bc=w0.bc, iters=2, limiter=True)
     out = oracle.run(p, steps, w0.psi, w0.cx, w0.cy, w0.cz, w0.g)
-    seed = 2.0 * workloads.config5_weights(w0.shape) * out
+    seed = 2.0 * workloads.cost_weights(w0.shape) * out
     _say("[adjoint] 256x128x60, 3 steps: oracle reverse sweep")
     want = oracle.adjoint(p, steps, w0.psi, w0.cx, w0.cy, w0.cz, w0.g, seed)
     got = mp.adjoint(*[_dev(a) for a in (w0.psi, w0.cx, w0.cy, w0.cz, w0.g)], _dev(seed), steps,
@@ -119,7 +119,7 @@ def test_config5_grid_matches_oracle_reverse_sweep():
 
 
 def _fd_directions(mp, torch, w0, psi0, steps, n_dir, eps, iters, limiter, seed=50):
-    w = workloads.config5_weights(w0.shape)
+    w = workloads.cost_weights(w0.shape)
     dev = [_dev(a) for a in (psi0, w0.cx, w0.cy, w0.cz, w0.g)]
     wd = _dev(w)
     kw = dict(iters=iters, limiter=limiter, bc=w0.bc)
@@ -150,7 +150,7 @@ def _fd_directions(mp, torch, w0, psi0, steps, n_dir, eps, iters, limiter, seed=
     return np.array(rels)
 
 
-def test_config5_finite_differences():
+def test_adjoint_256x128x60_finite_differences():
     """The configured check: 256x128x60, solid-body winds, limiter, 2 passes,
     20 steps, J = sum(w psi_T^2), checkpoints every 5 steps, central
     differences (eps 1e-6) on 16 random directions in (psi0, C), C directions
@@ -163,7 +163,7 @@ def test_config5_finite_differences():
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    w0 = workloads.config2()
+    w0 = workloads.latlon_solid_body()
     rels = _fd_directions(mp, torch, w0, w0.psi, 20, 16, 1e-6, 2, True)
     assert np.median(rels) <= 2e-2 and rels.max() <= 5e-2
 
@@ -174,12 +174,12 @@ def test_smooth_field_finite_differences():
     and central differences agree closely.  The bound, 2e-4 (measured
     6e-6..7e-5), is set by the faces where the perturbation moves an exactly
     zero antidiffusive velocity off zero: there the two one-sided slopes of the
-    donor flux differ by O(eps), against 1e-3..1e-2 for the kinked config-5
+    donor flux differ by O(eps), against 1e-3..1e-2 for the kinked 256x128x60 case
     field."""
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    w0 = workloads.config2()
+    w0 = workloads.latlon_solid_body()
     psi0 = 0.5 + np.broadcast_to(workloads.cosine_bell(w0.shape[2], w0.shape[1])[None], w0.shape).copy()
     rels = _fd_directions(mp, torch, w0, psi0, 10, 6, 1e-6, 2, False, seed=51)
     assert rels.max() <= 2e-4

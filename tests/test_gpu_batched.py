@@ -151,15 +151,15 @@ def test_tuner_writes_cache(tmp_path, monkeypatch):
     assert any(not torch.equal(a, b["psi"]) for a, b in zip(before, probs))
 
 
-def test_config4_full_batch_sampled():
+def test_64_problem_batch_sampled():
     """The batched workload (64 problems, 1-8 tracers, FP32, 2 passes,
     limiter, 20 steps, graph): the three smallest problems checked tracer by
     tracer against the FP64 oracle; every tracer stays positive."""
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    probs_h = workloads.config4()
-    _say(f"[batched] config 4: {len(probs_h)} problems, "
+    probs_h = workloads.batched_problems()
+    _say(f"[batched] 64-problem batch: {len(probs_h)} problems, "
          f"{sum(p['psi'].size for p in probs_h) / 1e6:.0f} M tracer-cells")
     probs = [{k: torch.from_numpy(v).cuda() for k, v in p.items()} for p in probs_h]
     mp.run_batched(probs, 20, iters=2, limiter=True, graph=True)

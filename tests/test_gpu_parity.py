@@ -152,10 +152,10 @@ def test_mass_matches_exact_sum():
     assert abs(got - want) <= 1e-15 * abs(want)
 
 
-def test_config1_full_run(kernels):
+def test_gaussian_2d_64x64_full_run(kernels):
     torch = _torch()
     mp = _mp()
-    w = workloads.config1()
+    w = workloads.gaussian_2d()
     _say(f"[parity] {w.name} {w.steps} steps")
     p = oracle.RefProblem(64, 64, 1, bc=w.bc, iters=w.iters, limiter=w.limiter)
     want = oracle.run(p, w.steps, w.psi, w.cx, w.cy, w.cz, w.g)
@@ -165,10 +165,10 @@ def test_config1_full_run(kernels):
     assert _rel(t.cpu().numpy(), want) <= TOL64
 
 
-def test_config2_full_run(kernels):
+def test_latlon_256x128x60_full_run(kernels):
     torch = _torch()
     mp = _mp()
-    w = workloads.config2()
+    w = workloads.latlon_solid_body()
     _say(f"[parity] {w.name} {w.steps} steps, oracle threads={oracle.num_threads()}")
     p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
     want = oracle.run(p, w.steps, w.psi, w.cx, w.cy, w.cz, w.g)
@@ -183,12 +183,12 @@ def test_config2_full_run(kernels):
     assert abs(mp.mass(t, args[3]) - m0) <= 1e-13 * m0
 
 
-def test_config3_full_size_one_step():
+def test_latlon_1024x512x80_full_size_one_step():
     """The benchmark's workload (1024x512x80, 3 passes, limiter) at full size:
     two steps against the oracle, every cell compared."""
     torch = _torch()
     mp = _mp()
-    w = workloads.config3()
+    w = workloads.latlon_wave()
     _say(f"[parity] {w.name} 2 steps at full size")
     p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
     want = oracle.run(p, 2, w.psi, w.cx, w.cy, w.cz, w.g)
@@ -230,12 +230,12 @@ def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
         assert got.min() >= 0.0
 
 
-def test_fp32_config3_full_size():
+def test_fp32_latlon_1024x512x80_full_size():
     """1024x512x80, 3 passes, limiter: FP32 vs the FP64 oracle at full size
     (2 steps), positivity and FP64-accumulated mass."""
     torch = _torch()
     mp = _mp()
-    w = workloads.config3_fp32_inputs(workloads.config3())
+    w = workloads.rounded_to_fp32(workloads.latlon_wave())
     _say(f"[parity-f32] {w.name} 2 steps at full size")
     p = oracle.RefProblem(w.shape[2], w.shape[1], w.shape[0], bc=w.bc, iters=w.iters, limiter=w.limiter)
     want = oracle.run(p, 2, w.psi, w.cx, w.cy, w.cz, w.g)

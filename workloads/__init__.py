@@ -142,7 +142,7 @@ def cosine_bell(nx, ny, centre=(1.5 * math.pi, 0.0), radius=1.0 / 3.0, h=1.0):
 # The five workloads
 # ---------------------------------------------------------------------------
 
-def config1(n=64, steps=100):
+def gaussian_2d(n=64, steps=100):
     """2-D periodic n x n, constant Courant (0.25, 0.15), G = 1, Gaussian blob
     (amplitude 1, sigma 6 cells, background 0), 2 passes, no limiter."""
     shape = (1, n, n)
@@ -154,7 +154,7 @@ def config1(n=64, steps=100):
                     psi, np.full(shape, 0.25), np.full(shape, 0.15), np.zeros(shape), np.ones(shape))
 
 
-def config2(nx=256, ny=128, nz=60, steps=50, seed=2):
+def latlon_solid_body(nx=256, ny=128, nz=60, steps=50, seed=2):
     """Lat-lon 256x128x60, 2 passes, limiter on, G = cos(lat), solid-body winds
     (tilt 0.05 rad) scaled to max Courant 0.5, Cz = 0, cosine bell + U[0, 0.1)."""
     rng = np.random.default_rng(seed)
@@ -166,7 +166,7 @@ def config2(nx=256, ny=128, nz=60, steps=50, seed=2):
                     np.ascontiguousarray(psi), cx, cy, cz, metric(nx, ny, nz), meta)
 
 
-def config3(nx=1024, ny=512, nz=80, steps=50, seed=3, iters=3):
+def latlon_wave(nx=1024, ny=512, nz=80, steps=50, seed=3, iters=3):
     """Lat-lon 1024x512x80, 3 passes, limiter on, streamfunction winds
     Psi = -sin(lat) + 0.5 cos^3(lat) sin(2 lon) scaled to max Courant 0.6,
     lognormal(0, 1) tracer."""
@@ -178,7 +178,7 @@ def config3(nx=1024, ny=512, nz=80, steps=50, seed=3, iters=3):
                     psi, cx, cy, cz, metric(nx, ny, nz), meta)
 
 
-def config3_fp32_inputs(w: Workload) -> Workload:
+def rounded_to_fp32(w: Workload) -> Workload:
     """Inputs rounded to FP32 once, so FP32 and FP64 runs start from the same values."""
     r = w.astype(np.float32).astype(np.float64)
     r.name = w.name
@@ -199,18 +199,18 @@ def random_problem(shape, bc, seed, courant=0.3, gmin=0.5, positive=True, cz=Tru
     return psi, cx, cy, czz, g
 
 
-def config5_weights(shape, seed=5):
+def cost_weights(shape, seed=5):
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=shape)
 
 
-def config4(count=64, seed=4, dtype=np.float32, max_courant=0.5):
+def batched_problems(count=64, seed=4, dtype=np.float32, max_courant=0.5):
     """Batched workload: `count` lat-lon problems of uneven sizes, each with
-    1-8 lognormal(0, 1) tracers sharing its winds (config-3 streamfunction
+    1-8 lognormal(0, 1) tracers sharing its winds (the 1024x512x80 workload's streamfunction
     family at max Courant 0.5) and metric; FP32, 2 passes, limiter, 20 steps.
     Returns a list of dicts: psi (ntracers, nz, ny, nx), cx, cy, cz, g."""
     rng = np.random.default_rng(seed + 1000)
     out = []
-    for nx, ny, nz, nt in batched_problems(count, seed):
+    for nx, ny, nz, nt in batch_sizes(count, seed):
         cx, cy, cz, _ = stream_winds(nx, ny, nz, "wave", max_courant)
         g = metric(nx, ny, nz)
         psi = np.exp(rng.standard_normal((nt, nz, ny, nx), dtype=np.float64)).astype(dtype)
@@ -219,7 +219,7 @@ def config4(count=64, seed=4, dtype=np.float32, max_courant=0.5):
     return out
 
 
-def batched_problems(count=64, seed=4):
+def batch_sizes(count=64, seed=4):
     """Sizes and tracer counts of the batched workload: nx in U{64..512},
     ny in U{32..256}, nz in U{20..80}, 1-8 tracers."""
     rng = np.random.default_rng(seed)
