@@ -15,6 +15,9 @@
 // The antidiffusive velocity reads ~20 inputs per face, so its adjoint runs
 // in two kernels: the first evaluates each face's partial derivatives times
 // the face's adjoint once (nine values per face), the second gathers them.
+// The limiter's adjoint also runs in two: the limited velocities and beta's
+// per-cell terms (k_adj_limit_beta), then the gathers of in / out and of the
+// bounds (k_adj_inout_bounds).
 #pragma once
 
 #include "common.hpp"
@@ -129,22 +132,22 @@ __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Limited velocities:  lvl -> lut (=), lbup (=), lbdn (=)
+// Limited velocities:  lvl -> lut (=) at the cell's own faces, and the
+// adjoints of beta_up and beta_dn at the cell (gup, gdn)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adj_limit(Geo g, const double* __restrict__ ut, const double* __restrict__ vt,
-                                                   const double* __restrict__ wt, const double* __restrict__ bup,
-                                                   const double* __restrict__ bdn, const double* __restrict__ lvx,
-                                                   const double* __restrict__ lvy, const double* __restrict__ lvz,
-                                                   double* __restrict__ lux, double* __restrict__ luy,
-                                                   double* __restrict__ luz, double* __restrict__ lbup,
-                                                   double* __restrict__ lbdn)
+__device__ __forceinline__ void adj_limit_cell(const Geo& g, const Cell& c, const double* __restrict__ ut,
+                                               const double* __restrict__ vt, const double* __restrict__ wt,
+                                               const double* __restrict__ bup, const double* __restrict__ bdn,
+                                               const double* __restrict__ lvx, const double* __restrict__ lvy,
+                                               const double* __restrict__ lvz, double* __restrict__ lux,
+                                               double* __restrict__ luy, double* __restrict__ luz, double& gup,
+                                               double& gdn)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     const double* U3[3] = {ut, vt, wt};
     const double* L3[3] = {lvx, lvy, lvz};
     double* O3[3] = {lux, luy, luz};
-    double gup = 0.0, gdn = 0.0;
+    gup = 0.0;
+    gdn = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         // own face: c is its left cell
@@ -174,8 +177,6 @@ __global__ void __launch_bounds__(256) k_adj_limit(Geo g, const double* __restri
             if (U < 0.0 && first_min3(bup[ql], bdn[c.q]) == 2) gdn += lam * U;
         }
     }
-    lbup[c.q] = gup;
-    lbdn[c.q] = gdn;
 }
 
 // ---------------------------------------------------------------------------
@@ -242,16 +243,13 @@ __global__ void __launch_bounds__(256) k_bounds(Geo g, const double* __restrict_
     code[2 * c.q + 1] = (unsigned char)an;
 }
 
-// (lmx, lmn) -> lpsin (+=, or = for its first contribution), lphi (+=): each
-// cell x collects from the distinct cells whose cross contains it, where x is
-// the recorded first maximal / minimal entry.
-__global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* __restrict__ code,
-                                                    const double* __restrict__ lmx, const double* __restrict__ lmn,
-                                                    double* __restrict__ lpsin, double* __restrict__ lphi,
-                                                    int assign_psin)
+// (lmx, lmn) -> the cell's shares gp (of psi^n) and gf (of the iterate):
+// each cell x collects from the distinct cells whose cross contains it, where
+// x is the recorded first maximal / minimal entry.
+__device__ __forceinline__ void adj_bounds_cell(const Geo& g, const Cell& c, const unsigned char* __restrict__ code,
+                                                const double* __restrict__ lmx, const double* __restrict__ lmn,
+                                                double& gp, double& gf)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     // Fast path: every axis periodic with >= 3 cells, or c >= 1 away from a
     // closed end.  Then the seven cells whose cross contains c are distinct,
     // and candidate y = c + step(m) reaches c only through its entry
@@ -265,7 +263,7 @@ __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* 
     if (fast) {
         const long long st[3] = {1, g.sy, g.sz};
         const int cc[3] = {c.i, c.j, c.k};
-        double gp = 0.0, gf = 0.0;
+        gp = gf = 0.0;
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
             long long yq = c.q;
@@ -282,16 +280,13 @@ __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* 
             if (am % 7 == want) (am < 7 ? gp : gf) += lmx[yq];
             if (an % 7 == want) (an < 7 ? gp : gf) += lmn[yq];
         }
-        if (assign_psin) lpsin[c.q] = gp;
-        else lpsin[c.q] += gp;
-        lphi[c.q] += gf;
         return;
     }
     // the cells whose cross contains c (the cross is symmetric)
     const Pt cand[7] = {mapped(g, c.i, c.j, c.k),     mapped(g, c.i - 1, c.j, c.k), mapped(g, c.i + 1, c.j, c.k),
                         mapped(g, c.i, c.j - 1, c.k), mapped(g, c.i, c.j + 1, c.k), mapped(g, c.i, c.j, c.k - 1),
                         mapped(g, c.i, c.j, c.k + 1)};
-    double gp = 0.0, gf = 0.0;
+    gp = gf = 0.0;
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
         bool dup = false;
@@ -303,17 +298,14 @@ __global__ void __launch_bounds__(256) k_adj_bounds(Geo g, const unsigned char* 
         if (cross_entry(g, y.i, y.j, y.k, am % 7) == c.q) (am < 7 ? gp : gf) += lmx[y.q];
         if (cross_entry(g, y.i, y.j, y.k, an % 7) == c.q) (an < 7 ? gp : gf) += lmn[y.q];
     }
-    if (assign_psin) lpsin[c.q] = gp;
-    else lpsin[c.q] += gp;
-    lphi[c.q] += gf;
 }
 
 // ---------------------------------------------------------------------------
 // Limiter coefficients beta_up = (mx - phi) G / (in + eps),
 // beta_dn = (phi - mn) G / (out + eps).
-// Kernel 1 (per cell): the adjoints of in and out (lin, lout), of mx and mn,
-// and beta's direct dependence on phi.  Kernel 2 (gather): in and out's
-// dependence on phi and on the antidiffusive velocities.
+// Per cell (adj_beta1_cell): the adjoints of in and out (lin, lout), of mx
+// and mn, and beta's direct dependence on phi.  Gathered (adj_inout_cell):
+// in and out's dependence on phi and on the antidiffusive velocities.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void in_out(const Geo& g, const Cell& c, const double* __restrict__ phi,
                                        const double* const U3[3], double& in, double& out)
@@ -336,17 +328,14 @@ __device__ __forceinline__ void in_out(const Geo& g, const Cell& c, const double
     out = (fout[0] + fout[1]) + fout[2];
 }
 
-__global__ void __launch_bounds__(256) k_adj_beta1(Geo g, double eps, const double* __restrict__ phi,
-                                                   const double* __restrict__ ut, const double* __restrict__ vt,
-                                                   const double* __restrict__ wt, const double* __restrict__ mx,
-                                                   const double* __restrict__ mn, const double* __restrict__ gm,
-                                                   const double* __restrict__ lbup, const double* __restrict__ lbdn,
-                                                   double* __restrict__ lin, double* __restrict__ lout,
-                                                   double* __restrict__ lmx, double* __restrict__ lmn,
-                                                   double* __restrict__ lphi)
+__device__ __forceinline__ void adj_beta1_cell(const Geo& g, const Cell& c, double eps, const double* __restrict__ phi,
+                                               const double* __restrict__ ut, const double* __restrict__ vt,
+                                               const double* __restrict__ wt, const double* __restrict__ mx,
+                                               const double* __restrict__ mn, const double* __restrict__ gm,
+                                               double gu, double gd, double* __restrict__ lin,
+                                               double* __restrict__ lout, double* __restrict__ lmx,
+                                               double* __restrict__ lmn, double* __restrict__ lphi)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     const double* U3[3] = {ut, vt, wt};
     double in, out;
     in_out(g, c, phi, U3, in, out);
@@ -354,7 +343,6 @@ __global__ void __launch_bounds__(256) k_adj_beta1(Geo g, double eps, const doub
     const double G = gm[c.q], pc = phi[c.q];
     const double bu = ((mx[c.q] - pc) * G) * rin;
     const double bd = ((pc - mn[c.q]) * G) * rout;
-    const double gu = lbup[c.q], gd = lbdn[c.q];
     lmx[c.q] = gu * G * rin;
     lmn[c.q] = -(gd * G * rout);
     lphi[c.q] += -gu * G * rin + gd * G * rout;
@@ -364,14 +352,12 @@ __global__ void __launch_bounds__(256) k_adj_beta1(Geo g, double eps, const doub
 
 // in(c)  = sum_a [U(c-1/2)]+ phi(c-1) - [U(c+1/2)]- phi(c+1)
 // out(c) = sum_a ([U(c+1/2)]+ - [U(c-1/2)]-) phi(c)
-__global__ void __launch_bounds__(256) k_adj_beta2(Geo g, const double* __restrict__ phi, const double* __restrict__ ut,
-                                                   const double* __restrict__ vt, const double* __restrict__ wt,
-                                                   const double* __restrict__ lin, const double* __restrict__ lout,
-                                                   double* __restrict__ lphi, double* __restrict__ lux,
-                                                   double* __restrict__ luy, double* __restrict__ luz)
+__device__ __forceinline__ double adj_inout_cell(const Geo& g, const Cell& c, const double* __restrict__ phi,
+                                                 const double* __restrict__ ut, const double* __restrict__ vt,
+                                                 const double* __restrict__ wt, const double* __restrict__ lin,
+                                                 const double* __restrict__ lout, double* __restrict__ lux,
+                                                 double* __restrict__ luy, double* __restrict__ luz)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     const double* U3[3] = {ut, vt, wt};
     double* L3[3] = {lux, luy, luz};
     const double pc = phi[c.q];
@@ -399,7 +385,54 @@ __global__ void __launch_bounds__(256) k_adj_beta2(Geo g, const double* __restri
             acc += -lin[ql] * pneg(U) - lout[c.q] * pneg(U);
         }
     }
-    lphi[c.q] += acc;
+    return acc;
+}
+
+// The limiter's adjoint in two gathers.  First, per cell: the limited
+// velocities' adjoint (lvl -> lut, =) and, from the adjoints of beta it
+// yields (kept in registers), those of in, out, mx and mn (=) and beta's
+// direct dependence on the iterate (lphi, +=).
+__global__ void __launch_bounds__(256) k_adj_limit_beta(Geo g, double eps, const double* __restrict__ phi,
+                                                        const double* __restrict__ ut, const double* __restrict__ vt,
+                                                        const double* __restrict__ wt, const double* __restrict__ bup,
+                                                        const double* __restrict__ bdn, const double* __restrict__ lvx,
+                                                        const double* __restrict__ lvy, const double* __restrict__ lvz,
+                                                        const double* __restrict__ mx, const double* __restrict__ mn,
+                                                        const double* __restrict__ gm, double* __restrict__ lux,
+                                                        double* __restrict__ luy, double* __restrict__ luz,
+                                                        double* __restrict__ lin, double* __restrict__ lout,
+                                                        double* __restrict__ lmx, double* __restrict__ lmn,
+                                                        double* __restrict__ lphi)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    double gup, gdn;
+    adj_limit_cell(g, c, ut, vt, wt, bup, bdn, lvx, lvy, lvz, lux, luy, luz, gup, gdn);
+    adj_beta1_cell(g, c, eps, phi, ut, vt, wt, mx, mn, gm, gup, gdn, lin, lout, lmx, lmn, lphi);
+}
+
+// Second, gathering from the neighbours: in and out's dependence on the
+// iterate and on the antidiffusive velocities (lphi +=, lut +=), and the
+// bounds' routing to psi^n (lpsin: = for its first contribution in a step,
+// else +=) and to the iterate (lphi +=).
+__global__ void __launch_bounds__(256) k_adj_inout_bounds(Geo g, const double* __restrict__ phi,
+                                                          const double* __restrict__ ut, const double* __restrict__ vt,
+                                                          const double* __restrict__ wt, const double* __restrict__ lin,
+                                                          const double* __restrict__ lout,
+                                                          const unsigned char* __restrict__ code,
+                                                          const double* __restrict__ lmx, const double* __restrict__ lmn,
+                                                          double* __restrict__ lux, double* __restrict__ luy,
+                                                          double* __restrict__ luz, double* __restrict__ lpsin,
+                                                          double* __restrict__ lphi, int assign_psin)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double acc = adj_inout_cell(g, c, phi, ut, vt, wt, lin, lout, lux, luy, luz);
+    double gp, gf;
+    adj_bounds_cell(g, c, code, lmx, lmn, gp, gf);
+    if (assign_psin) lpsin[c.q] = gp;
+    else lpsin[c.q] += gp;
+    lphi[c.q] += acc + gf;
 }
 
 // ---------------------------------------------------------------------------

@@ -468,10 +468,10 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     // checkpoints + segment states + for each step of a segment and each
     // corrective pass a record (the pass's input iterate, U~ x3, V x3, beta
     // x2) + the bounds of the step being reversed (mx, mn, extremal-entry
-    // codes per pass) + a sink for the segment's last output + 18 adjoint
-    // fields (cur, prev, psin, V x3, Vprev x3, U~ x3, beta x2, lin, lout,
-    // lmx, lmn) + antidiffusive slots (27) + a zero field and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 18 + 27 + 2;
+    // codes per pass) + a sink for the segment's last output + 16 adjoint
+    // fields (cur, prev, psin, V x3, Vprev x3, U~ x3, lin, lout, lmx, lmn) +
+    // antidiffusive slots (27) + a zero field and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 16 + 27 + 2;
     return L;
 }
 
@@ -572,8 +572,6 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     double* lv[3] = {field(), field(), field()};
     double* lvp[3] = {field(), field(), field()};
     double* lut[3] = {field(), field(), field()};
-    double* lbu = field();
-    double* lbd = field();
     double* lin = field();
     double* lout = field();
     double* lmx = field();
@@ -652,13 +650,11 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                                                     1, m == M);
                 const double* lu3[3] = {lv[0], lv[1], lv[2]};   // unlimited: dJ/dU~ = dJ/dV
                 if (p->limiter) {
-                    A::k_adj_limit<<<grd, blk, 0, st>>>(g, U3[0], U3[1], U3[2], R.bu[m], R.bd[m], lv[0], lv[1],
-                                                        lv[2], lut[0], lut[1], lut[2], lbu, lbd);
-                    A::k_adj_beta1<<<grd, blk, 0, st>>>(g, eps, ph, U3[0], U3[1], U3[2], mx[m], mn[m], gm, lbu, lbd,
-                                                        lin, lout, lmx, lmn, lprev);
-                    A::k_adj_beta2<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, lprev, lut[0], lut[1],
-                                                        lut[2]);
-                    A::k_adj_bounds<<<grd, blk, 0, st>>>(g, code[m], lmx, lmn, lpsin, lprev, m == M);
+                    A::k_adj_limit_beta<<<grd, blk, 0, st>>>(g, eps, ph, U3[0], U3[1], U3[2], R.bu[m], R.bd[m], lv[0],
+                                                             lv[1], lv[2], mx[m], mn[m], gm, lut[0], lut[1], lut[2],
+                                                             lin, lout, lmx, lmn, lprev);
+                    A::k_adj_inout_bounds<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx,
+                                                               lmn, lut[0], lut[1], lut[2], lpsin, lprev, m == M);
                     for (int a = 0; a < 3; ++a) lu3[a] = lut[a];
                 }
                 double* tgt[3];
