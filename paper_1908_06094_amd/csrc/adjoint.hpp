@@ -734,13 +734,6 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
     }
 }
 
-__global__ void __launch_bounds__(256) k_axpy(long long n, double a, const double* __restrict__ x,
-                                              double* __restrict__ y)
-{
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) y[q] += a * x[q];
-}
-
 #pragma clang fp contract(on)
 
 }  // namespace adj
