@@ -54,14 +54,18 @@ def bytes_per_cell_step(elem, with_cz=True):
     return elem * ((5 if with_cz else 4) + 1)
 
 
-def traffic_record(kernel_src_sha, dtype):
+def traffic_record(kernel_src_sha, dtype, workload):
     """Counter-derived HBM bytes per launch of the fused pass, if the committed
-    record was taken on the kernel source as it is now (else None)."""
+    record was taken on this workload and on the kernel source as it is now
+    (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_fused_pass_{dtype}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_sha256") != kernel_src_sha:
+        return None
+    grid = rec.get("workload", "").split(" ")[0]     # e.g. latlon-1024x512x80
+    if not grid or not workload.startswith(grid):
         return None
     return rec.get("bytes_per_launch")
 
@@ -79,7 +83,7 @@ def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
         avg_s = pass_ms * 1e-3 / pass_n
         ops = model.corrective_pass_ops(w.limiter)
         kernel = "fused corrective pass (k_pass)"
-        traffic = traffic_record(profsum.kernel_source_sha(), dtype)
+        traffic = traffic_record(profsum.kernel_source_sha(), dtype, w.name)
     else:
         # no per-launch records (per-stage path, or a graph replay): one step
         bytes_per_launch = bytes_per_cell_step(elem) * w.cells
