@@ -37,3 +37,30 @@ def test_op_counts_consistent():
     assert s3.total == d.total + 2 * c.total
     # the peak used for the ALU roofline: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz
     assert abs(model.FP64_VALU_OPS_PEAK - 39.3216e12) < 1e9
+
+
+def test_traffic_record_matches_kernel_source_and_workload():
+    """The counter record under profiles/ is attached to a bench line only for
+    the workload it was taken on and while the pass kernel's source is the one
+    it was taken on (its recorded hash)."""
+    import json
+    import os
+
+    import bench
+    from paper_1908_06094_amd import profsum
+
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        "traffic_fused_pass_f64.json")
+    rec = json.load(open(path))
+    sha = profsum.kernel_source_sha()
+    if rec["source_sha256"] == sha:
+        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave") == rec["bytes_per_launch"]
+    else:   # a stale record (the kernel changed since the counters were taken) is never attached
+        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave") is None
+    sha = rec["source_sha256"]
+    assert bench.traffic_record(sha, "f64", "latlon-256x128x60-solid-body") is None
+    assert bench.traffic_record("0" * 64, "f64", "latlon-1024x512x80-wave") is None
+    # calibrated counter bytes per launch: fetched x copy factor + written, averaged over the two passes
+    f = rec["copy_calibration"]["fetch_factor"]
+    kib = [rec["fetch_kib_per_dispatch"][k] * f + rec["write_kib_per_dispatch"][k] for k in rec["fetch_kib_per_dispatch"]]
+    assert abs(sum(kib) / len(kib) * 1024 - rec["bytes_per_launch"]) <= 1e-6 * rec["bytes_per_launch"]
