@@ -605,14 +605,22 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     Timed tm(MPDATA_KERNEL_STAGE, st);
 
     // forward sweep: psi^{cK} into checkpoint c, other states ping-pong
-    // between two scratch fields (the adjoint ones, unused until the reverse)
+    // between two scratch fields (the adjoint ones, unused until the
+    // reverse).  The last segment's steps keep their records and states
+    // right away, so the reverse sweep does not recompute that segment.
     copy(ckpt[0], psi0);
+    const int last0 = (L.segs - 1) * K;
     const double* cur = ckpt[0];
     double* pp[2] = {lprev, lpsin};
     for (int s = 0; s < nsteps; ++s) {
-        const bool store = (s + 1) % K == 0 && (s + 1) / K < L.segs;
-        double* dst = store ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
-        if (int rc = step_record(p, cur, dst, cx, cy, cz, gm, rec[0], st)) return rc;   // records unused here
+        const int r = s - last0;
+        double* dst;
+        if (r >= 0)
+            dst = s + 1 < nsteps ? seg[r + 1] : pp[0];
+        else
+            dst = (s + 1) % K == 0 ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
+        // before the last segment the records are scratch
+        if (int rc = step_record(p, cur, dst, cx, cy, cz, gm, rec[r >= 0 ? r : 0], st)) return rc;
         cur = dst;
     }
     if (psiT && cur != psiT) copy(psiT, cur);
@@ -623,15 +631,19 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     for (int sg = L.segs - 1; sg >= 0; --sg) {
         const int s0 = sg * K;
         const int s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
+        // step r of the segment starts from state(r)
+        auto state = [&](int r) -> const double* { return r == 0 ? ckpt[sg] : seg[r]; };
         // the segment's steps again from its checkpoint, by the same kernels
-        // as the forward sweep, keeping each step's intermediates
-        copy(seg[0], ckpt[sg]);
-        for (int r = 0; r < s1 - s0; ++r)
-            if (int rc = step_record(p, seg[r], r + 1 < s1 - s0 ? seg[r + 1] : sink, cx, cy, cz, gm, rec[r], st))
-                return rc;
+        // as the forward sweep, keeping each step's intermediates (the last
+        // segment's are kept from the forward sweep)
+        if (sg < L.segs - 1)
+            for (int r = 0; r < s1 - s0; ++r)
+                if (int rc = step_record(p, state(r), r + 1 < s1 - s0 ? seg[r + 1] : sink, cx, cy, cz, gm, rec[r],
+                                         st))
+                    return rc;
         for (int r = s1 - s0 - 1; r >= 0; --r) {
             const AdjRec& R = rec[r];
-            const double* psin = seg[r];
+            const double* psin = state(r);
             // the step's bounds and the first extremal entries they came from
             if (p->limiter)
                 for (int m = 2; m <= M; ++m)
