@@ -41,12 +41,14 @@ def _margins_intact(whole, nbytes):
     return bool((h[:PAD] == CANARY).all() and (h[PAD + nbytes:] == CANARY).all())
 
 
-@pytest.mark.parametrize("dtype,iters,lim", [("f64", 3, True), ("f32", 3, True), ("f64", 2, False)])
-def test_step_and_run_write_only_their_buffers(dtype, iters, lim):
+@pytest.mark.parametrize("dtype,iters,lim,shape", [("f64", 3, True, (5, 37, 131)), ("f32", 3, True, (5, 37, 131)),
+                                                   ("f64", 2, False, (5, 37, 131)), ("f64", 3, True, (5, 30, 1)),
+                                                   ("f32", 2, True, (130, 3, 5))])
+def test_step_and_run_write_only_their_buffers(dtype, iters, lim, shape):
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    shape, bc = (5, 37, 131), (P, C, C)
+    bc = (P, C, C)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     elem = 8 if dtype == "f64" else 4
     print(f"[canary] step/run {dtype} shape={shape} iters={iters} limiter={lim}", flush=True)

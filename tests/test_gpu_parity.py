@@ -67,6 +67,9 @@ CASES = [
     ((4, 1, 200), (P, C, C), 3, True),
     ((2, 17, 70), (P, C, C), 3, True),     # segments prime from levels below the bottom (clamped)
     ((2, 9, 40), (P, P, P), 2, True),      # ... and wrapped
+    ((5, 30, 1), (C, P, C), 3, True),      # one column in x
+    ((130, 3, 5), (P, C, C), 2, True),     # tall column over a tiny plane
+    ((4, 12, 40), (P, C, C), 8, True),     # the largest pass count
 ]
 
 
@@ -211,7 +214,7 @@ TOL32 = 3e-5
 
 
 @pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6], CASES[8],
-                                                CASES[10], CASES[11], CASES[12]])
+                                                CASES[10], CASES[11], CASES[12], CASES[13], CASES[15]])
 def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
     torch = _torch()
     mp = _mp()
