@@ -39,6 +39,11 @@ def _say(msg):
     ((6, 13, 17), (P, C, P), 3, True, 4, 4),
     ((1, 3, 2), (P, P, P), 3, True, 2, 1),
     ((5, 10, 24), (P, C, C), 3, False, 3, 2),
+    ((3, 1, 40), (P, C, C), 2, True, 3, 2),    # one row: every y face a wall, dJ/dCy = 0
+    ((4, 20, 1), (C, P, C), 3, True, 3, 1),    # one column
+    ((2, 2, 3), (C, C, C), 3, True, 3, 2),     # every cell next to a closed end
+    ((40, 4, 6), (P, C, C), 2, True, 4, 2),    # tall column over a tiny plane
+    ((3, 6, 16), (P, C, C), 8, True, 2, 1),    # the largest pass count
 ])
 def test_adjoint_matches_oracle(shape, bc, iters, lim, steps, k):
     torch = _torch()
