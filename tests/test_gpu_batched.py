@@ -29,7 +29,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-SHAPES = [(5, 19, 70, 2), (3, 40, 131, 1), (7, 13, 64, 3), (1, 1, 1, 2), (4, 25, 61, 1)]
+SHAPES = [(5, 19, 70, 2), (3, 40, 131, 1), (7, 13, 64, 3), (1, 1, 1, 2), (4, 25, 61, 1), (6, 30, 1, 2), (90, 2, 5, 1)]
 
 
 def _batch(dtype, seed=0):
