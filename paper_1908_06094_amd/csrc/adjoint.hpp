@@ -444,27 +444,34 @@ __global__ void __launch_bounds__(256) k_adj_inout_bounds(Geo g, const double* _
 // Kernel 1 stores, per face (axis a, left cell y), lambda times:
 //   s0 dU~/dpR, s1 dU~/dpL, s2/s3 dU~/dSp_1, dU~/dSm_1, s4/s5 the same for
 //   the second transverse axis, s6/s7 dU~/dV_t of each of the four faces
-//   of transverse axis t, s8 dU~/dU.
+//   of transverse axis t.  lambda dU~/dU, read only at the face itself, goes
+//   straight into the velocity adjoint (assigned when assign_vel, else
+//   added; a closed wall's unused slot gets 0 when assigned), to which
+//   kernel 2 then adds the transverse terms.
 // ---------------------------------------------------------------------------
-constexpr int kSlots = 9;
+constexpr int kSlots = 8;
 
 __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const double* __restrict__ phi,
                                                        const double* __restrict__ u, const double* __restrict__ v,
                                                        const double* __restrict__ w, const double* __restrict__ gm,
                                                        const double* __restrict__ lux, const double* __restrict__ luy,
                                                        const double* __restrict__ luz, double* __restrict__ slots,
-                                                       long long field)
+                                                       long long field, double* __restrict__ lu,
+                                                       double* __restrict__ lv, double* __restrict__ lw,
+                                                       bool assign_vel)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
     const double* vel[3] = {u, v, w};
     const double* lam3[3] = {lux, luy, luz};
+    double* lvel[3] = {lu, lv, lw};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double* s = slots + (long long)a * kSlots * field + c.q;
-        const long long fo = face_idx(g, a, c.i, c.j, c.k);
+        const long long fo = face_idx(g, a, c.i, c.j, c.k);   // c.q when valid
         if (fo < 0) {
             for (int e = 0; e < kSlots; ++e) s[e * field] = 0.0;
+            if (lvel[a] && assign_vel) lvel[a][c.q] = 0.0;   // a closed wall's unused slot
             continue;
         }
         int R[3] = {c.i, c.j, c.k};
@@ -512,7 +519,10 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
             s[(3 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
             s[(6 + q) * field] = 0.25 * (lam * dS * B[q]);
         }
-        s[8 * field] = lam * dU;
+        if (lvel[a]) {
+            if (assign_vel) lvel[a][fo] = lam * dU;
+            else lvel[a][fo] += lam * dU;
+        }
     }
 }
 
@@ -580,8 +590,7 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
 
 __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
                                                        double* __restrict__ lphi, double* __restrict__ lu,
-                                                       double* __restrict__ lv, double* __restrict__ lw,
-                                                       int assign_vel)
+                                                       double* __restrict__ lv, double* __restrict__ lw)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
@@ -631,7 +640,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             if (!lvel[t]) continue;
-            double accv = slots[((long long)t * kSlots + 8) * field + x];
+            double accv = 0.0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (a == t) continue;
@@ -641,8 +650,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                 // face (t, x) is read by faces (a, y) at y = x, x - a, x + t, x - a + t
                 accv += (s6[x] + s6[x + da]) + (s6[x + dt] + s6[x + da + dt]);
             }
-            if (assign_vel) lvel[t][x] = accv;
-            else lvel[t][x] += accv;
+            lvel[t][x] += accv;
         }
         return;
     }
@@ -678,11 +686,8 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
     for (int t = 0; t < 3; ++t) {
         if (!lvel[t]) continue;
         const long long fx = face_idx(g, t, c.i, c.j, c.k);
-        if (fx < 0) {
-            if (assign_vel) lvel[t][x] = 0.0;   // a closed wall's unused slot
-            continue;
-        }
-        double accv = slots[((long long)t * kSlots + 8) * field + x];
+        if (fx < 0) continue;   // a closed wall's unused slot (kernel 1 wrote it)
+        double accv = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (a == t) continue;
@@ -729,8 +734,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                 if (hits) accv += hits * slots[((long long)a * kSlots + 6 + q) * field + y];
             }
         }
-        if (assign_vel) lvel[t][fx] = accv;
-        else lvel[t][fx] += accv;
+        lvel[t][fx] += accv;
     }
 }
 

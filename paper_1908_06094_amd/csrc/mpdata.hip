@@ -470,8 +470,9 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     // x2) + the bounds of the step being reversed (mx, mn, extremal-entry
     // codes per pass) + a sink for the segment's last output + 16 adjoint
     // fields (cur, prev, psin, V x3, Vprev x3, U~ x3, lin, lout, lmx, lmn) +
-    // antidiffusive slots (27) + a zero field and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 16 + 27 + 2;
+    // antidiffusive slots (3 axes x kSlots) + a zero field and a dJ/dcz scratch
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 16 +
+               (size_t)3 * mpdata::adj::kSlots + 2;
     return L;
 }
 
@@ -577,7 +578,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     double* lmx = field();
     double* lmn = field();
     double* slots = field();
-    next += 26;                       // the 27 slot fields are contiguous
+    next += 3 * mpdata::adj::kSlots - 1;   // the slot fields are contiguous
     double* zero_w = field();
     double* dcz_scratch = field();
     const long long slot_stride = (long long)(L.fb / sizeof(double));
@@ -672,8 +673,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                 double* tgt[3];
                 for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
                 A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lu3[0], lu3[1],
-                                                        lu3[2], slots, slot_stride);
-                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2], m > 2);
+                                                        lu3[2], slots, slot_stride, tgt[0], tgt[1], tgt[2], m > 2);
+                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
                 std::swap(lcur, lprev);
                 for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
             }
