@@ -442,29 +442,31 @@ __global__ void __launch_bounds__(256) k_adj_inout_bounds(Geo g, const double* _
 //   Sp = phi(R+t) + phi(L+t), Sm = phi(R-t) + phi(L-t),
 //   Vb_t = (V_t(L) + V_t(R) + V_t(L-t) + V_t(R-t))/4, Gf = (G(L) + G(R))/2.
 // Kernel 1 stores, per face (axis a, left cell y), lambda times:
-//   s0 dU~/dpR, s1 dU~/dpL, s2/s3 dU~/dSp_1, dU~/dSm_1, s4/s5 the same for
-//   the second transverse axis, s6/s7 dU~/dV_t of each of the four faces
-//   of transverse axis t.  lambda dU~/dU, read only at the face itself, goes
-//   straight into the velocity adjoint (assigned when assign_vel, else
-//   added; a closed wall's unused slot gets 0 when assigned), to which
-//   kernel 2 then adds the transverse terms.
+//   s0 dU~/dpR, s1/s2 dU~/dSp_1, dU~/dSm_1, s3/s4 the same for the second
+//   transverse axis, s5/s6 dU~/dV_t of each of the four faces of transverse
+//   axis t.  The two terms that belong to the face's own cell and face go
+//   straight into the adjoints instead: lambda dU~/dpL is added to dJ/dphi
+//   at y, and lambda dU~/dU to the velocity adjoint (assigned when
+//   assign_vel, else added; a closed wall's unused slot gets 0 when
+//   assigned).  Kernel 2 then adds the gathered terms to both.
 // ---------------------------------------------------------------------------
-constexpr int kSlots = 8;
+constexpr int kSlots = 7;
 
 __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const double* __restrict__ phi,
                                                        const double* __restrict__ u, const double* __restrict__ v,
                                                        const double* __restrict__ w, const double* __restrict__ gm,
                                                        const double* __restrict__ lux, const double* __restrict__ luy,
                                                        const double* __restrict__ luz, double* __restrict__ slots,
-                                                       long long field, double* __restrict__ lu,
-                                                       double* __restrict__ lv, double* __restrict__ lw,
-                                                       bool assign_vel)
+                                                       long long field, double* __restrict__ lphi,
+                                                       double* __restrict__ lu, double* __restrict__ lv,
+                                                       double* __restrict__ lw, bool assign_vel)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
     const double* vel[3] = {u, v, w};
     const double* lam3[3] = {lux, luy, luz};
     double* lvel[3] = {lu, lv, lw};
+    double own = 0.0;   // lambda dU~/dpL of the cell's three faces
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double* s = slots + (long long)a * kSlots * field + c.q;
@@ -510,20 +512,21 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
         const double gA = lam * dA;
         const double r2 = rD0 * rD0;
         s[0 * field] = gA * (2.0 * pL + eps) * r2;
-        s[1 * field] = -(gA * (2.0 * pR + eps) * r2);
+        own += -(gA * (2.0 * pR + eps) * r2);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double gB = lam * dS * Vb[q];
             const double rt2 = rDt[q] * rDt[q];
-            s[(2 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) * rt2);
-            s[(3 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
-            s[(6 + q) * field] = 0.25 * (lam * dS * B[q]);
+            s[(1 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) * rt2);
+            s[(2 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
+            s[(5 + q) * field] = 0.25 * (lam * dS * B[q]);
         }
         if (lvel[a]) {
             if (assign_vel) lvel[a][fo] = lam * dU;
             else lvel[a][fo] += lam * dU;
         }
     }
+    lphi[c.q] += own;
 }
 
 // Kernel 2: each cell x gathers the slots of the faces that read phi(x), and
@@ -534,7 +537,9 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
 // dJ/dphi at cell x from the faces along axis A (the general path of
 // k_adj_antidiff2): the distinct faces y whose 10 stencil positions (L, R,
 // L+-t1, R+-t1, L+-t2, R+-t2 after the halo rule) include x, each position
-// that is x adding that position's partial derivative.
+// that is x adding that position's partial derivative.  Position L is the
+// cell y itself, so it is x only for the face y = x, whose term kernel 1
+// has added already.
 template <int A>
 __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const int (&Yt)[3][3],
                                                             const int (&Tt)[3][3][3], const Cell& c,
@@ -547,7 +552,7 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
     for (int e = 0; e < 2; ++e) {
         off[e][0] = off[e][1] = off[e][2] = 0;
         off[e][A] = e;
-        slot_of[e] = e == 1 ? 0 : 1;
+        slot_of[e] = 0;   // R (L, e = 0, is never looked up)
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -559,7 +564,7 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
                 off[n][0] = off[n][1] = off[n][2] = 0;
                 off[n][A] = e;
                 off[n][q == 0 ? t1 : t2] = h == 0 ? 1 : -1;
-                slot_of[n] = 2 + 2 * q + h;
+                slot_of[n] = 1 + 2 * q + h;
             }
     const int xc[3] = {c.i, c.j, c.k};
     const int nA = extent(g, A), clA = closed(g, A);
@@ -578,7 +583,7 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
         const int ya = A == 0 ? yi : (A == 1 ? yj : yk);
         if (dup || (clA && ya >= nA - 1)) continue;     // counted already / wall: U~ is the constant 0
 #pragma unroll
-        for (int e = 0; e < 10; ++e) {
+        for (int e = 1; e < 10; ++e) {
             const bool hit = Tt[0][off[m][0] + 1][off[e][0] + 1] == xc[0] &&
                              Tt[1][off[m][1] + 1][off[e][1] + 1] == xc[1] &&
                              Tt[2][off[m][2] + 1][off[e][2] + 1] == xc[2];
@@ -624,16 +629,16 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const double* s = slots + (long long)a * kSlots * field;
             const long long da = shifted(a, 1);
-            // L = x (dU~/dpL), R = x (face at x - a)
-            acc += s[1 * field + x] + s[0 * field + x + da];
+            // R = x (face at x - a); L = x was added by kernel 1
+            acc += s[0 * field + x + da];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int t = q == 0 ? t1 : t2;
                 const long long dp = shifted(t, 1), dm = shifted(t, -1);
                 // x = L + t or R + t: faces at x - t and x - t - a (slot Sp)
-                acc += s[(2 + 2 * q) * field + x + dp] + s[(2 + 2 * q) * field + x + dp + da];
+                acc += s[(1 + 2 * q) * field + x + dp] + s[(1 + 2 * q) * field + x + dp + da];
                 // x = L - t or R - t: faces at x + t and x + t - a (slot Sm)
-                acc += s[(3 + 2 * q) * field + x + dm] + s[(3 + 2 * q) * field + x + dm + da];
+                acc += s[(2 + 2 * q) * field + x + dm] + s[(2 + 2 * q) * field + x + dm + da];
             }
         }
         lphi[x] += acc;
@@ -645,7 +650,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
             for (int a = 0; a < 3; ++a) {
                 if (a == t) continue;
                 const int q = (t == (a == 0 ? 1 : 0)) ? 0 : 1;
-                const double* s6 = slots + ((long long)a * kSlots + 6 + q) * field;
+                const double* s6 = slots + ((long long)a * kSlots + 5 + q) * field;
                 const long long da = shifted(a, 1), dt = shifted(t, -1);
                 // face (t, x) is read by faces (a, y) at y = x, x - a, x + t, x - a + t
                 accv += (s6[x] + s6[x + da]) + (s6[x + dt] + s6[x + da + dt]);
@@ -731,7 +736,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __re
                 rm[t] -= 1;
                 int hits = (face_idx(g, t, yi, yj, yk) == fx) + (face_idx(g, t, ry[0], ry[1], ry[2]) == fx) +
                            (face_idx(g, t, lm[0], lm[1], lm[2]) == fx) + (face_idx(g, t, rm[0], rm[1], rm[2]) == fx);
-                if (hits) accv += hits * slots[((long long)a * kSlots + 6 + q) * field + y];
+                if (hits) accv += hits * slots[((long long)a * kSlots + 5 + q) * field + y];
             }
         }
         lvel[t][fx] += accv;

@@ -673,7 +673,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                 double* tgt[3];
                 for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
                 A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lu3[0], lu3[1],
-                                                        lu3[2], slots, slot_stride, tgt[0], tgt[1], tgt[2], m > 2);
+                                                        lu3[2], slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2],
+                                                        m > 2);
                 A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
                 std::swap(lcur, lprev);
                 for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
