@@ -64,6 +64,21 @@ def summarise(path):
     return from_csv(path) if path.endswith(".csv") else from_db(path)
 
 
+def last_launches_mean(path, kernel_substr, n):
+    """Mean duration (us) of the last `n` dispatches of the kernel whose name
+    contains `kernel_substr`, from a rocprofv3 per-dispatch kernel trace CSV
+    directory: the timed launches of a run whose first ones are warm-up."""
+    hits = glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True)
+    spans = []
+    with open(hits[0]) as f:
+        for r in csv.DictReader(f):
+            if kernel_substr in r["Kernel_Name"]:
+                spans.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    spans.sort()
+    last = spans[-n:]
+    return sum(e - s for s, e in last) / len(last) / 1e3
+
+
 def counters(path):
     """{kernel name: {counter: mean value per dispatch}} from a rocprofv3 counter CSV directory."""
     hits = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
