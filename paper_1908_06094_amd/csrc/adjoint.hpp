@@ -14,10 +14,12 @@
 //
 // The antidiffusive velocity reads ~20 inputs per face, so its adjoint runs
 // in two kernels: the first evaluates each face's partial derivatives times
-// the face's adjoint once (nine values per face), the second gathers them.
-// The limiter's adjoint also runs in two: the limited velocities and beta's
-// per-cell terms (k_adj_limit_beta), then the gathers of in / out and of the
-// bounds (k_adj_inout_bounds).
+// the face's adjoint once (seven values per face kept, two applied at
+// once), the second gathers them.  In a limited pass the donor-cell adjoint
+// and the limiter's run in two kernels: the donor-cell terms with the
+// limited velocities' and beta's per-cell terms (k_adj_donor_limit_beta),
+// then the gathers of in / out and of the bounds (k_adj_inout_bounds).  An
+// unlimited pass and the first (donor-cell) pass use k_adj_donor.
 #pragma once
 
 #include "common.hpp"
@@ -132,19 +134,18 @@ __global__ void __launch_bounds__(256) k_adj_donor(Geo g, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Limited velocities:  lvl -> lut (=) at the cell's own faces, and the
+// Limited velocities: from their adjoints at the cell's own and left faces,
+// the antidiffusive velocities' adjoint (lut, =) at the own faces, and the
 // adjoints of beta_up and beta_dn at the cell (gup, gdn)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void adj_limit_cell(const Geo& g, const Cell& c, const double* __restrict__ ut,
                                                const double* __restrict__ vt, const double* __restrict__ wt,
                                                const double* __restrict__ bup, const double* __restrict__ bdn,
-                                               const double* __restrict__ lvx, const double* __restrict__ lvy,
-                                               const double* __restrict__ lvz, double* __restrict__ lux,
-                                               double* __restrict__ luy, double* __restrict__ luz, double& gup,
-                                               double& gdn)
+                                               const double (&lam_own)[3], const double (&lam_left)[3],
+                                               double* __restrict__ lux, double* __restrict__ luy,
+                                               double* __restrict__ luz, double& gup, double& gdn)
 {
     const double* U3[3] = {ut, vt, wt};
-    const double* L3[3] = {lvx, lvy, lvz};
     double* O3[3] = {lux, luy, luz};
     gup = 0.0;
     gdn = 0.0;
@@ -156,7 +157,7 @@ __device__ __forceinline__ void adj_limit_cell(const Geo& g, const Cell& c, cons
             int r[3] = {c.i, c.j, c.k};
             r[a] += 1;
             const long long qr = at(g, r[0], r[1], r[2]);
-            const double U = U3[a][fo], lam = L3[a][fo];
+            const double U = U3[a][fo], lam = lam_own[a];
             const double up = min2(1.0, min2(bdn[c.q], bup[qr]));
             const double dn = min2(1.0, min2(bup[c.q], bdn[qr]));
             O3[a][fo] = lam * (stp(U) * up + stn(U) * dn);
@@ -172,7 +173,7 @@ __device__ __forceinline__ void adj_limit_cell(const Geo& g, const Cell& c, cons
         const long long fl = face_idx(g, a, l[0], l[1], l[2]);
         if (fl >= 0) {
             const long long ql = at(g, l[0], l[1], l[2]);
-            const double U = U3[a][fl], lam = L3[a][fl];
+            const double U = U3[a][fl], lam = lam_left[a];
             if (U > 0.0 && first_min3(bdn[ql], bup[c.q]) == 2) gup += lam * U;
             if (U < 0.0 && first_min3(bup[ql], bdn[c.q]) == 2) gdn += lam * U;
         }
@@ -388,26 +389,66 @@ __device__ __forceinline__ double adj_inout_cell(const Geo& g, const Cell& c, co
     return acc;
 }
 
-// The limiter's adjoint in two gathers.  First, per cell: the limited
-// velocities' adjoint (lvl -> lut, =) and, from the adjoints of beta it
-// yields (kept in registers), those of in, out, mx and mn (=) and beta's
+// The limiter's adjoint in two gathers.  First, per cell, fused with the
+// pass's donor-cell adjoint: dJ/dphi's donor-cell terms (lphi, =) and the
+// adjoints of the limited velocities at the cell's own and left faces, formed
+// in registers: their donor-cell part from lnext, phi and G (at the left face
+// the same expression, operand for operand, that the left cell forms for its
+// own face, so both agree bitwise) plus, unless assign_vel, what the next
+// pass's antidiffusive-velocity adjoint left in lvx/lvy/lvz.  From them the
+// antidiffusive velocities' adjoint (lut, =) and, from the adjoints of beta
+// it yields (kept in registers), those of in, out, mx and mn (=) and beta's
 // direct dependence on the iterate (lphi, +=).
-__global__ void __launch_bounds__(256) k_adj_limit_beta(Geo g, double eps, const double* __restrict__ phi,
-                                                        const double* __restrict__ ut, const double* __restrict__ vt,
-                                                        const double* __restrict__ wt, const double* __restrict__ bup,
-                                                        const double* __restrict__ bdn, const double* __restrict__ lvx,
-                                                        const double* __restrict__ lvy, const double* __restrict__ lvz,
-                                                        const double* __restrict__ mx, const double* __restrict__ mn,
-                                                        const double* __restrict__ gm, double* __restrict__ lux,
-                                                        double* __restrict__ luy, double* __restrict__ luz,
-                                                        double* __restrict__ lin, double* __restrict__ lout,
-                                                        double* __restrict__ lmx, double* __restrict__ lmn,
-                                                        double* __restrict__ lphi)
+__global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
+    Geo g, double eps, const double* __restrict__ phi, const double* __restrict__ vlx, const double* __restrict__ vly,
+    const double* __restrict__ vlz, const double* __restrict__ gm, const double* __restrict__ lnext,
+    const double* __restrict__ lvx, const double* __restrict__ lvy, const double* __restrict__ lvz, int assign_vel,
+    const double* __restrict__ ut, const double* __restrict__ vt, const double* __restrict__ wt,
+    const double* __restrict__ bup, const double* __restrict__ bdn, const double* __restrict__ mx,
+    const double* __restrict__ mn, double* __restrict__ lux, double* __restrict__ luy, double* __restrict__ luz,
+    double* __restrict__ lin, double* __restrict__ lout, double* __restrict__ lmx, double* __restrict__ lmn,
+    double* __restrict__ lphi)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
+    const double* vel[3] = {vlx, vly, vlz};
+    const double* L3[3] = {lvx, lvy, lvz};
+    double acc = lnext[c.q];
+    const double mu_c = lnext[c.q] / gm[c.q];
+    double lam_own[3], lam_left[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // own face c+1/2: the flux leaves c and enters r
+        lam_own[a] = 0.0;
+        const long long fo = face_idx(g, a, c.i, c.j, c.k);
+        if (fo >= 0) {
+            int r[3] = {c.i, c.j, c.k};
+            r[a] += 1;
+            const long long qr = at(g, r[0], r[1], r[2]);
+            const double lamf = lnext[qr] / gm[qr] - mu_c;
+            const double vv = vel[a][fo];
+            acc += ppos(vv) * lamf;
+            lam_own[a] = (stp(vv) * phi[c.q] + stn(vv) * phi[qr]) * lamf;
+            if (!assign_vel) lam_own[a] += L3[a][fo];
+        }
+        // left face c-1/2: c is the right cell of the flux; its donor part
+        // is the same expression the left cell forms for its own face
+        lam_left[a] = 0.0;
+        int l[3] = {c.i, c.j, c.k};
+        l[a] -= 1;
+        const long long fl = face_idx(g, a, l[0], l[1], l[2]);
+        if (fl >= 0) {
+            const long long ql = at(g, l[0], l[1], l[2]);
+            const double lamf = mu_c - lnext[ql] / gm[ql];
+            const double vv = vel[a][fl];
+            acc += pneg(vv) * lamf;
+            lam_left[a] = (stp(vv) * phi[ql] + stn(vv) * phi[c.q]) * lamf;
+            if (!assign_vel) lam_left[a] += L3[a][fl];
+        }
+    }
+    lphi[c.q] = acc;
     double gup, gdn;
-    adj_limit_cell(g, c, ut, vt, wt, bup, bdn, lvx, lvy, lvz, lux, luy, luz, gup, gdn);
+    adj_limit_cell(g, c, ut, vt, wt, bup, bdn, lam_own, lam_left, lux, luy, luz, gup, gdn);
     adj_beta1_cell(g, c, eps, phi, ut, vt, wt, mx, mn, gm, gup, gdn, lin, lout, lmx, lmn, lphi);
 }
 
