@@ -223,25 +223,20 @@ __device__ __forceinline__ long long cross_entry(const Geo& g, int i, int j, int
 // The bounds and, in code[2q] / code[2q+1], the first maximal / minimal
 // entry e of the 14 (psi^n at the cross's 7 cells, then the iterate), the
 // entry through which the adjoint of mx / mn flows.
-__global__ void __launch_bounds__(256) k_bounds(Geo g, const double* __restrict__ psin, const double* __restrict__ phi,
-                                                double* __restrict__ mx, double* __restrict__ mn,
-                                                unsigned char* __restrict__ code)
+__device__ __forceinline__ void bounds_cell(const Geo& g, const Cell& c, const double* __restrict__ psin,
+                                            const double* __restrict__ phi, double& hi, double& lo, int& am, int& an)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     long long idx[7];
     cross7(g, c.i, c.j, c.k, idx);
-    double hi = psin[idx[0]], lo = hi;
-    int am = 0, an = 0;
+    hi = psin[idx[0]];
+    lo = hi;
+    am = 0;
+    an = 0;
     for (int e = 1; e < 14; ++e) {
         const double v = (e < 7 ? psin : phi)[idx[e % 7]];
         if (v > hi) { hi = v; am = e; }
         if (v < lo) { lo = v; an = e; }
     }
-    mx[c.q] = hi;
-    mn[c.q] = lo;
-    code[2 * c.q] = (unsigned char)am;
-    code[2 * c.q + 1] = (unsigned char)an;
 }
 
 // (lmx, lmn) -> the cell's shares gp (of psi^n) and gf (of the iterate):
@@ -331,9 +326,9 @@ __device__ __forceinline__ void in_out(const Geo& g, const Cell& c, const double
 
 __device__ __forceinline__ void adj_beta1_cell(const Geo& g, const Cell& c, double eps, const double* __restrict__ phi,
                                                const double* __restrict__ ut, const double* __restrict__ vt,
-                                               const double* __restrict__ wt, const double* __restrict__ mx,
-                                               const double* __restrict__ mn, const double* __restrict__ gm,
-                                               double gu, double gd, double* __restrict__ lin,
+                                               const double* __restrict__ wt, double mx, double mn,
+                                               const double* __restrict__ gm, double gu, double gd,
+                                               double* __restrict__ lin,
                                                double* __restrict__ lout, double* __restrict__ lmx,
                                                double* __restrict__ lmn, double* __restrict__ lphi)
 {
@@ -342,8 +337,8 @@ __device__ __forceinline__ void adj_beta1_cell(const Geo& g, const Cell& c, doub
     in_out(g, c, phi, U3, in, out);
     const double rin = rcp_nr(in + eps), rout = rcp_nr(out + eps);
     const double G = gm[c.q], pc = phi[c.q];
-    const double bu = ((mx[c.q] - pc) * G) * rin;
-    const double bd = ((pc - mn[c.q]) * G) * rout;
+    const double bu = ((mx - pc) * G) * rin;
+    const double bd = ((pc - mn) * G) * rout;
     lmx[c.q] = gu * G * rin;
     lmn[c.q] = -(gd * G * rout);
     lphi[c.q] += -gu * G * rin + gd * G * rout;
@@ -404,8 +399,8 @@ __global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
     const double* __restrict__ vlz, const double* __restrict__ gm, const double* __restrict__ lnext,
     const double* __restrict__ lvx, const double* __restrict__ lvy, const double* __restrict__ lvz, int assign_vel,
     const double* __restrict__ ut, const double* __restrict__ vt, const double* __restrict__ wt,
-    const double* __restrict__ bup, const double* __restrict__ bdn, const double* __restrict__ mx,
-    const double* __restrict__ mn, double* __restrict__ lux, double* __restrict__ luy, double* __restrict__ luz,
+    const double* __restrict__ bup, const double* __restrict__ bdn, const double* __restrict__ psin,
+    unsigned char* __restrict__ code, double* __restrict__ lux, double* __restrict__ luy, double* __restrict__ luz,
     double* __restrict__ lin, double* __restrict__ lout, double* __restrict__ lmx, double* __restrict__ lmn,
     double* __restrict__ lphi)
 {
@@ -449,7 +444,14 @@ __global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
     lphi[c.q] = acc;
     double gup, gdn;
     adj_limit_cell(g, c, ut, vt, wt, bup, bdn, lam_own, lam_left, lux, luy, luz, gup, gdn);
-    adj_beta1_cell(g, c, eps, phi, ut, vt, wt, mx, mn, gm, gup, gdn, lin, lout, lmx, lmn, lphi);
+    // the bounds of the cell and the first extremal entries they came from
+    // (code: read by the bounds' gather in k_adj_inout_bounds)
+    double hi, lo;
+    int am, an;
+    bounds_cell(g, c, psin, phi, hi, lo, am, an);
+    code[2 * c.q] = (unsigned char)am;
+    code[2 * c.q + 1] = (unsigned char)an;
+    adj_beta1_cell(g, c, eps, phi, ut, vt, wt, hi, lo, gm, gup, gdn, lin, lout, lmx, lmn, lphi);
 }
 
 // Second, gathering from the neighbours: in and out's dependence on the

@@ -467,11 +467,11 @@ AdjLayout adj_layout(const mpdata_problem* p, int nsteps, int K)
     L.M = p->iters;
     // checkpoints + segment states + for each step of a segment and each
     // corrective pass a record (the pass's input iterate, U~ x3, V x3, beta
-    // x2) + the bounds of the step being reversed (mx, mn, extremal-entry
-    // codes per pass) + a sink for the segment's last output + 16 adjoint
+    // x2) + the extremal-entry codes of the bounds of the step being
+    // reversed, per pass + a sink for the segment's last output + 16 adjoint
     // fields (cur, prev, psin, V x3, Vprev x3, U~ x3, lin, lout, lmx, lmn) +
     // antidiffusive slots (3 axes x kSlots) + a zero field and a dJ/dcz scratch
-    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)3 * (L.M - 1) + 1 + 16 +
+    L.fields = (size_t)L.segs + (size_t)K + (size_t)K * 9 * (L.M - 1) + (size_t)(L.M - 1) + 1 + 16 +
                (size_t)3 * mpdata::adj::kSlots + 2;
     return L;
 }
@@ -559,13 +559,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
             }
         }
     }
-    std::vector<double*> mx(M + 1, nullptr), mn(M + 1, nullptr);
     std::vector<unsigned char*> code(M + 1, nullptr);   // 2 bytes per cell in a field of 8
-    for (int m = 2; m <= M; ++m) {
-        mx[m] = field();
-        mn[m] = field();
-        code[m] = (unsigned char*)field();
-    }
+    for (int m = 2; m <= M; ++m) code[m] = (unsigned char*)field();
     double* sink = field();
     double* lcur = field();
     double* lprev = field();
@@ -645,12 +640,6 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
         for (int r = s1 - s0 - 1; r >= 0; --r) {
             const AdjRec& R = rec[r];
             const double* psin = state(r);
-            // the step's bounds and the first extremal entries they came from
-            if (p->limiter)
-                for (int m = 2; m <= M; ++m)
-                    A::k_bounds<<<grd, blk, 0, st>>>(g, psin, R.phis[m - 1], mx[m], mn[m], code[m]);
-            if (int rc = launch_status("adjoint bounds")) return rc;
-
             // reverse through the passes.  No buffer is cleared: the first
             // contribution each adjoint buffer receives in a step assigns it.
             for (int m = M; m >= 2; --m) {
@@ -667,7 +656,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                     // the donor-cell adjoint fused with the limiter's per-cell terms
                     A::k_adj_donor_limit_beta<<<grd, blk, 0, st>>>(g, eps, ph, V3[0], V3[1], V3[2], gm, lcur, lv[0],
                                                                    lv[1], lv[2], m == M, U3[0], U3[1], U3[2],
-                                                                   R.bu[m], R.bd[m], mx[m], mn[m], lut[0], lut[1],
+                                                                   R.bu[m], R.bd[m], psin, code[m], lut[0], lut[1],
                                                                    lut[2], lin, lout, lmx, lmn, lprev);
                     A::k_adj_inout_bounds<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx,
                                                                lmn, lut[0], lut[1], lut[2], lpsin, lprev, m == M);
