@@ -18,8 +18,10 @@
 // once), the second gathers them.  In a limited pass the donor-cell adjoint
 // and the limiter's run in two kernels: the donor-cell terms with the
 // limited velocities' and beta's per-cell terms (k_adj_donor_limit_beta),
-// then the gathers of in / out and of the bounds (k_adj_inout_bounds).  An
-// unlimited pass and the first (donor-cell) pass use k_adj_donor.
+// then the gathers of in / out and of the bounds together with the first
+// antidiffusive-velocity kernel (k_adj_inout_bounds_antidiff1).  An
+// unlimited pass and the first (donor-cell) pass use k_adj_donor, and an
+// unlimited pass k_adj_antidiff1 on its own.
 #pragma once
 
 #include "common.hpp"
@@ -351,15 +353,14 @@ __device__ __forceinline__ void adj_beta1_cell(const Geo& g, const Cell& c, doub
 __device__ __forceinline__ double adj_inout_cell(const Geo& g, const Cell& c, const double* __restrict__ phi,
                                                  const double* __restrict__ ut, const double* __restrict__ vt,
                                                  const double* __restrict__ wt, const double* __restrict__ lin,
-                                                 const double* __restrict__ lout, double* __restrict__ lux,
-                                                 double* __restrict__ luy, double* __restrict__ luz)
+                                                 const double* __restrict__ lout, double (&dl)[3])
 {
     const double* U3[3] = {ut, vt, wt};
-    double* L3[3] = {lux, luy, luz};
     const double pc = phi[c.q];
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        dl[a] = 0.0;
         int l[3] = {c.i, c.j, c.k}, r[3] = {c.i, c.j, c.k};
         l[a] -= 1;
         r[a] += 1;
@@ -371,8 +372,8 @@ __device__ __forceinline__ double adj_inout_cell(const Geo& g, const Cell& c, co
             // c is the left cell of its own face: inflow term of r, outflow term of c
             acc += lin[qr] * ppos(U) + lout[c.q] * ppos(U);
             // the face's own adjoint: in(r), in(c), out(c), out(r)
-            L3[a][fo] += lin[qr] * stp(U) * pc - lin[c.q] * stn(U) * phi[qr] + lout[c.q] * stp(U) * pc -
-                         lout[qr] * stn(U) * phi[qr];
+            dl[a] = lin[qr] * stp(U) * pc - lin[c.q] * stn(U) * phi[qr] + lout[c.q] * stp(U) * pc -
+                    lout[qr] * stn(U) * phi[qr];
         }
         if (fl >= 0) {
             const long long ql = at(g, l[0], l[1], l[2]);
@@ -445,7 +446,7 @@ __global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
     double gup, gdn;
     adj_limit_cell(g, c, ut, vt, wt, bup, bdn, lam_own, lam_left, lux, luy, luz, gup, gdn);
     // the bounds of the cell and the first extremal entries they came from
-    // (code: read by the bounds' gather in k_adj_inout_bounds)
+    // (code: read by the bounds' gather in k_adj_inout_bounds_antidiff1)
     double hi, lo;
     int am, an;
     bounds_cell(g, c, psin, phi, hi, lo, am, an);
@@ -458,25 +459,6 @@ __global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
 // iterate and on the antidiffusive velocities (lphi +=, lut +=), and the
 // bounds' routing to psi^n (lpsin: = for its first contribution in a step,
 // else +=) and to the iterate (lphi +=).
-__global__ void __launch_bounds__(256) k_adj_inout_bounds(Geo g, const double* __restrict__ phi,
-                                                          const double* __restrict__ ut, const double* __restrict__ vt,
-                                                          const double* __restrict__ wt, const double* __restrict__ lin,
-                                                          const double* __restrict__ lout,
-                                                          const unsigned char* __restrict__ code,
-                                                          const double* __restrict__ lmx, const double* __restrict__ lmn,
-                                                          double* __restrict__ lux, double* __restrict__ luy,
-                                                          double* __restrict__ luz, double* __restrict__ lpsin,
-                                                          double* __restrict__ lphi, int assign_psin)
-{
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
-    const double acc = adj_inout_cell(g, c, phi, ut, vt, wt, lin, lout, lux, luy, luz);
-    double gp, gf;
-    adj_bounds_cell(g, c, code, lmx, lmn, gp, gf);
-    if (assign_psin) lpsin[c.q] = gp;
-    else lpsin[c.q] += gp;
-    lphi[c.q] += acc + gf;
-}
 
 // ---------------------------------------------------------------------------
 // Antidiffusive velocity
@@ -495,19 +477,16 @@ __global__ void __launch_bounds__(256) k_adj_inout_bounds(Geo g, const double* _
 // ---------------------------------------------------------------------------
 constexpr int kSlots = 7;
 
-__global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const double* __restrict__ phi,
-                                                       const double* __restrict__ u, const double* __restrict__ v,
-                                                       const double* __restrict__ w, const double* __restrict__ gm,
-                                                       const double* __restrict__ lux, const double* __restrict__ luy,
-                                                       const double* __restrict__ luz, double* __restrict__ slots,
-                                                       long long field, double* __restrict__ lphi,
-                                                       double* __restrict__ lu, double* __restrict__ lv,
-                                                       double* __restrict__ lw, bool assign_vel)
+// Kernel 1's work at one cell, given the adjoints lam of the antidiffusive
+// velocities at its three own faces; returns lambda dU~/dpL summed over them.
+__device__ __forceinline__ double antidiff1_cell(const Geo& g, const Cell& c, double eps, const double* __restrict__ phi,
+                                                 const double* __restrict__ u, const double* __restrict__ v,
+                                                 const double* __restrict__ w, const double* __restrict__ gm,
+                                                 const double (&lam_face)[3], double* __restrict__ slots,
+                                                 long long field, double* __restrict__ lu, double* __restrict__ lv,
+                                                 double* __restrict__ lw, bool assign_vel)
 {
-    Cell c;
-    if (!cell_of_thread(g, c)) return;
     const double* vel[3] = {u, v, w};
-    const double* lam3[3] = {lux, luy, luz};
     double* lvel[3] = {lu, lv, lw};
     double own = 0.0;   // lambda dU~/dpL of the cell's three faces
 #pragma unroll
@@ -521,7 +500,7 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
         }
         int R[3] = {c.i, c.j, c.k};
         R[a] += 1;
-        const double lam = lam3[a][c.q];
+        const double lam = lam_face[a];
         const double pL = phi[c.q], pR = phi[at(g, R[0], R[1], R[2])];
         const double D0 = (pR + pL) + eps;
         const double rD0 = rcp_nr(D0);
@@ -569,7 +548,52 @@ __global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const 
             else lvel[a][fo] += lam * dU;
         }
     }
-    lphi[c.q] += own;
+    return own;
+}
+
+__global__ void __launch_bounds__(256) k_adj_antidiff1(Geo g, double eps, const double* __restrict__ phi,
+                                                       const double* __restrict__ u, const double* __restrict__ v,
+                                                       const double* __restrict__ w, const double* __restrict__ gm,
+                                                       const double* __restrict__ lux, const double* __restrict__ luy,
+                                                       const double* __restrict__ luz, double* __restrict__ slots,
+                                                       long long field, double* __restrict__ lphi,
+                                                       double* __restrict__ lu, double* __restrict__ lv,
+                                                       double* __restrict__ lw, bool assign_vel)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    const double lam[3] = {lux[c.q], luy[c.q], luz[c.q]};
+    lphi[c.q] += antidiff1_cell(g, c, eps, phi, u, v, w, gm, lam, slots, field, lu, lv, lw, assign_vel);
+}
+
+// A limited pass: the limiter's second gather (in / out and the bounds)
+// fused with kernel 1.  The antidiffusive velocities' adjoint at the cell's
+// own faces is what the limiter's first kernel left in lutx/luty/lutz plus
+// the in / out terms formed here, kept in registers for kernel 1's work (the
+// same sums, in the same order, as adding it to lut and reading it back).
+// The bounds route to psi^n (lpsin: = when assign_psin, else +=); dJ/dphi
+// gains the in / out and bound terms and then kernel 1's own-cell term.
+__global__ void __launch_bounds__(256) k_adj_inout_bounds_antidiff1(
+    Geo g, double eps, const double* __restrict__ phi, const double* __restrict__ ut, const double* __restrict__ vt,
+    const double* __restrict__ wt, const double* __restrict__ lin, const double* __restrict__ lout,
+    const unsigned char* __restrict__ code, const double* __restrict__ lmx, const double* __restrict__ lmn,
+    const double* __restrict__ lutx, const double* __restrict__ luty, const double* __restrict__ lutz,
+    double* __restrict__ lpsin, int assign_psin, const double* __restrict__ pu, const double* __restrict__ pv,
+    const double* __restrict__ pw, const double* __restrict__ gm, double* __restrict__ slots, long long field,
+    double* __restrict__ lphi, double* __restrict__ lu, double* __restrict__ lv, double* __restrict__ lw,
+    bool assign_vel)
+{
+    Cell c;
+    if (!cell_of_thread(g, c)) return;
+    double dl[3];
+    const double acc = adj_inout_cell(g, c, phi, ut, vt, wt, lin, lout, dl);
+    double gp, gf;
+    adj_bounds_cell(g, c, code, lmx, lmn, gp, gf);
+    if (assign_psin) lpsin[c.q] = gp;
+    else lpsin[c.q] += gp;
+    const double lam[3] = {lutx[c.q] + dl[0], luty[c.q] + dl[1], lutz[c.q] + dl[2]};
+    const double own = antidiff1_cell(g, c, eps, phi, pu, pv, pw, gm, lam, slots, field, lu, lv, lw, assign_vel);
+    lphi[c.q] = (lphi[c.q] + (acc + gf)) + own;
 }
 
 // Kernel 2: each cell x gathers the slots of the faces that read phi(x), and

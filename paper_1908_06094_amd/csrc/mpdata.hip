@@ -648,25 +648,28 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                 for (int a = 0; a < 3; ++a) prev[a] = m == 2 ? C3[a] : R.vl[3 * (m - 1) + a];
                 const double* U3[3] = {R.ut[3 * m], R.ut[3 * m + 1], R.ut[3 * m + 2]};
                 const double* V3[3] = {R.vl[3 * m], R.vl[3 * m + 1], R.vl[3 * m + 2]};
-                const double* lu3[3] = {lv[0], lv[1], lv[2]};   // unlimited: dJ/dU~ = dJ/dV
-                if (!p->limiter)
-                    A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1],
-                                                        lv[2], 1, m == M);
-                if (p->limiter) {
+                if (p->limiter)
                     // the donor-cell adjoint fused with the limiter's per-cell terms
                     A::k_adj_donor_limit_beta<<<grd, blk, 0, st>>>(g, eps, ph, V3[0], V3[1], V3[2], gm, lcur, lv[0],
                                                                    lv[1], lv[2], m == M, U3[0], U3[1], U3[2],
                                                                    R.bu[m], R.bd[m], psin, code[m], lut[0], lut[1],
                                                                    lut[2], lin, lout, lmx, lmn, lprev);
-                    A::k_adj_inout_bounds<<<grd, blk, 0, st>>>(g, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx,
-                                                               lmn, lut[0], lut[1], lut[2], lpsin, lprev, m == M);
-                    for (int a = 0; a < 3; ++a) lu3[a] = lut[a];
-                }
+                else
+                    A::k_adj_donor<<<grd, blk, 0, st>>>(g, ph, V3[0], V3[1], V3[2], gm, lcur, lprev, lv[0], lv[1],
+                                                        lv[2], 1, m == M);
                 double* tgt[3];
                 for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
-                A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lu3[0], lu3[1],
-                                                        lu3[2], slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2],
-                                                        m > 2);
+                if (p->limiter)
+                    // the limiter's in / out and bounds gather fused with the
+                    // antidiffusive velocities' first adjoint kernel
+                    A::k_adj_inout_bounds_antidiff1<<<grd, blk, 0, st>>>(
+                        g, eps, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx, lmn, lut[0], lut[1], lut[2], lpsin,
+                        m == M, prev[0], prev[1], prev[2], gm, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2],
+                        m > 2);
+                else   // unlimited: dJ/dU~ = dJ/dV
+                    A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lv[0],
+                                                            lv[1], lv[2], slots, slot_stride, lprev, tgt[0], tgt[1],
+                                                            tgt[2], m > 2);
                 A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
                 std::swap(lcur, lprev);
                 for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
