@@ -64,3 +64,20 @@ def test_traffic_record_matches_kernel_source_and_workload():
     f = rec["copy_calibration"]["fetch_factor"]
     kib = [rec["fetch_kib_per_dispatch"][k] * f + rec["write_kib_per_dispatch"][k] for k in rec["fetch_kib_per_dispatch"]]
     assert abs(sum(kib) / len(kib) * 1024 - rec["bytes_per_launch"]) <= 1e-6 * rec["bytes_per_launch"]
+
+
+def test_last_launches_mean_skips_warmup(tmp_path):
+    """The timed-launch mean of a per-dispatch trace: the last n dispatches of
+    the named kernel, whatever order the rows come in."""
+    from paper_1908_06094_amd import profsum
+
+    rows = ["\"Kind\",\"Kernel_Name\",\"Start_Timestamp\",\"End_Timestamp\""]
+    t = 0
+    for n, dur in enumerate([5000, 4000, 1000, 1100, 900, 1000]):       # ns; the first two are warm-up
+        rows.append(f"\"KERNEL_DISPATCH\",\"void k_pass<double, true>(Geo)\",{t},{t + dur}")
+        rows.append(f"\"KERNEL_DISPATCH\",\"void k_other(Geo)\",{t + dur},{t + dur + 7000}")
+        t += dur + 10000
+    body = [rows[0]] + rows[1:][::-1]                                   # rows out of order
+    (tmp_path / "run_kernel_trace.csv").write_text("\n".join(body) + "\n")
+    assert abs(profsum.last_launches_mean(str(tmp_path), "k_pass<double", 4) - 1.0) < 1e-12    # us
+    assert abs(profsum.last_launches_mean(str(tmp_path), "k_pass<double", 6) - 13000 / 6 / 1e3) < 1e-12
