@@ -660,7 +660,8 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
     return acc;
 }
 
-__global__ void __launch_bounds__(256) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
+// 6 waves per SIMD: 80 VGPRs with no spills (unbounded it takes 82, 5 waves)
+__global__ void __launch_bounds__(256, 6) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
                                                        double* __restrict__ lphi, double* __restrict__ lu,
                                                        double* __restrict__ lv, double* __restrict__ lw)
 {
