@@ -5,10 +5,20 @@ the non-oscillatory limiter, divergence-free streamfunction winds (max
 Courant 0.6), lognormal tracer.  One "step" advances every cell by one full
 MPDATA time step (all passes).  Inputs are resident in HBM before timing.
 
-Prints ONE JSON line.  Besides the headline value it carries
-  roofline      the dominant kernel's algorithmic HBM bytes per launch over its
-                average launch time (HIP events on the stream it runs on),
-                against the 8 TB/s HBM peak;
+Inputs are generated in FP64 and rounded to FP32 once, and the FP64 and
+FP32 runs both start from those values, so that their difference measures
+arithmetic precision only.
+
+Prints ONE JSON line.  Besides the headline value (FP64) it carries
+  roofline      the algorithmic HBM bytes of one cell-step (read psi, Cx, Cy,
+                Cz, G, write psi: 48 B in FP64, 24 B in FP32) times the cells
+                one launch of the dominant kernel processes, over that
+                kernel's mean launch time (HIP events on the stream it runs
+                on), against the 8 TB/s HBM peak; the step-level fraction
+                (the same bytes over the whole step's time) is beside it;
+  fp32          the same workload in FP32 storage and arithmetic: throughput,
+                the same roofline figures, and its error against the FP64
+                oracle (max and RMS, mass drift, min psi);
   cpu_baseline  the CPU oracle (plain C, OpenMP, FP64) timed on this host on a
                 bounded sample of the same workload.
 """
@@ -32,14 +42,10 @@ def log(msg):
 
 
 def make_workload(name, dtype):
-    import numpy as np
-
     import workloads
 
     if name == "latlon-1024x512x80":
-        w = workloads.latlon_wave()
-        if dtype == "f32":
-            w = workloads.rounded_to_fp32(w)
+        w = workloads.rounded_to_fp32(workloads.latlon_wave())
     elif name == "latlon-256x128x60":
         w = workloads.latlon_solid_body()
     elif name == "2d-64x64":
@@ -71,36 +77,121 @@ def traffic_record(kernel_src_sha, dtype, workload):
 
 
 def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
-    """Roofline of the dominant kernel: the fused corrective pass (or, on the
-    per-stage path, all stage kernels of a step taken together)."""
+    """Roofline of the dominant kernel, the fused corrective pass (or, on the
+    per-stage path, all stage kernels of a step taken together, or one whole
+    step under a graph replay): the algorithmic bytes of one cell-step times
+    the cells one launch processes, over the mean launch time.  Returns that
+    record, the same launch time against this library's per-pass word model,
+    and the ALU figure."""
     from paper_1908_06094_amd import model, profsum
 
-    with_cz = True
+    step_bytes = bytes_per_cell_step(elem) * w.cells
     if pass_n:
-        # passes 2..iters-1 also write their limited velocities
-        words = [model.pass_kernel_words(m < w.iters, with_cz) for m in range(2, w.iters + 1)]
-        bytes_per_launch = sum(words) / len(words) * elem * w.cells
         avg_s = pass_ms * 1e-3 / pass_n
         ops = model.corrective_pass_ops(w.limiter)
         kernel = "fused corrective pass (k_pass)"
         traffic = traffic_record(profsum.kernel_source_sha(), dtype, w.name)
+        # passes 2..iters-1 also write their limited velocities
+        words = [model.pass_kernel_words(m < w.iters, True) for m in range(2, w.iters + 1)]
+        model_bytes = sum(words) / len(words) * elem * w.cells
     else:
-        # no per-launch records (per-stage path, or a graph replay): one step
-        bytes_per_launch = bytes_per_cell_step(elem) * w.cells
         avg_s = stage_ms * 1e-3 / max(stage_n, 1) if stage_n else ev_ms * 1e-3 / steps
         ops = model.step_ops(w.iters, w.limiter)
         kernel = "per-stage kernels of one step" if stage_n else "one whole step (HIP events around the replay)"
         traffic = None
-    achieved = bytes_per_launch / avg_s / 1e9
+        model_bytes = step_bytes
+    achieved = step_bytes / avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel, "bytes_per_launch": int(bytes_per_launch),
-            "avg_launch_us": round(avg_s * 1e6, 2)}
+            "traffic_source": (f"committed counter record profiles/traffic_fused_pass_{dtype}.json "
+                               "(FETCH_SIZE x copy factor + WRITE_SIZE per launch; its kernel-source hash matches)"
+                               if traffic is not None else None),
+            "kernel": kernel, "bytes_per_launch": int(step_bytes),
+            "bytes_rule": f"{bytes_per_cell_step(elem)} B per cell (read psi, Cx, Cy, Cz, G; write psi) x {w.cells} cells",
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "step_frac": round(step_bytes * steps / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    pass_model = {"bytes_per_launch": int(model_bytes),
+                  "rule": "the pass's own reads and writes: iterate, psi^n, 3 velocities, G; new iterate "
+                          "(+ 3 limited velocities when another pass follows)",
+                  "achieved_GBps": round(model_bytes / avg_s / 1e9, 1),
+                  "frac": round(model_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
     ops_s = ops.total * w.cells / avg_s
     alu = {"bound": "alu", "achieved": round(ops_s / 1e12, 3), "peak": round(model.FP64_VALU_OPS_PEAK / 1e12, 2),
            "unit": "T FP64 ops/s", "frac": round(ops_s / model.FP64_VALU_OPS_PEAK, 4),
            "ops_per_cell": ops.total, "divisions_per_cell": ops.divisions}
-    return roof, alu
+    return roof, pass_model, alu
+
+
+def time_forward(mp, torch, dev, w, dtype, steps, warmup, use_graph=False):
+    """`steps` steps of workload w in `dtype` after `warmup` steps, inputs
+    resident in HBM: wall and HIP-event times and the per-kernel launch times
+    recorded on the launch stream."""
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    psi = torch.from_numpy(w.psi).to(dev, tdt)
+    cx, cy, cz, g = (torch.from_numpy(a).to(dev, tdt) for a in (w.cx, w.cy, w.cz, w.g))
+    p = mp.problem_for(w.shape, w.bc, w.iters, w.limiter, dtype)
+    ws = torch.empty(mp.workspace_bytes(p, mp.MPDATA_OP_RUN), dtype=torch.uint8, device=dev)
+    kw = dict(iters=w.iters, limiter=w.limiter, bc=w.bc, workspace=ws)
+    stream = torch.cuda.current_stream(dev)
+    if warmup:
+        mp.run(psi, cx, cy, cz, g, warmup, **kw)
+    torch.cuda.synchronize()
+    log(f"[bench] {dtype}: warmup {warmup} steps done")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    graph = None
+    if use_graph:
+        # the K steps captured once on a side stream, then replayed
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                mp.run(psi, cx, cy, cz, g, steps, **kw)
+        stream.wait_stream(side)
+        graph.replay()               # one untimed replay
+        torch.cuda.synchronize()
+        log(f"[bench] captured {steps} steps in one graph")
+    torch.cuda.synchronize()
+    mp.timing_enable(True)          # HIP events around every kernel launch, on the launch stream
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    if graph is not None:
+        graph.replay()
+    else:
+        mp.run(psi, cx, cy, cz, g, steps, **kw)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mp.timing_enable(False)
+    r = {"wall": wall, "ev_ms": ev0.elapsed_time(ev1), "graph": graph is not None}
+    r["pass_ms"], r["pass_n"] = mp.timing_read(mp.MPDATA_KERNEL_PASS)
+    r["donor_ms"], r["donor_n"] = mp.timing_read(mp.MPDATA_KERNEL_DONOR)
+    r["stage_ms"], r["stage_n"] = mp.timing_read(mp.MPDATA_KERNEL_STAGE)
+    log(f"[bench] {dtype}: {steps} steps: wall {wall*1e3:.2f} ms, events {r['ev_ms']:.2f} ms; "
+        f"pass kernel {r['pass_n']} x {r['pass_ms'] / max(r['pass_n'], 1):.3f} ms, donor {r['donor_n']} x "
+        f"{r['donor_ms'] / max(r['donor_n'], 1):.3f} ms")
+    del psi, cx, cy, cz, g, ws
+    return r
+
+
+def gpu_accuracy(mp, torch, dev, w, dtype, n, want):
+    """n steps on the GPU in `dtype` from the workload's start against the
+    FP64 oracle's result `want` from the same start."""
+    import numpy as np
+
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    x = torch.from_numpy(w.psi).to(dev, tdt)
+    cx, cy, cz, g = (torch.from_numpy(a).to(dev, tdt) for a in (w.cx, w.cy, w.cz, w.g))
+    m0 = mp.mass(x, g, bc=w.bc)
+    mp.run(x, cx, cy, cz, g, n, iters=w.iters, limiter=w.limiter, bc=w.bc)
+    m1 = mp.mass(x, g, bc=w.bc)
+    got = x.double().cpu().numpy()
+    diff = got - want
+    return {"steps": n, "max_abs_err_rel": float(np.max(np.abs(diff)) / np.max(np.abs(want))),
+            "rms_err_rel": float(np.sqrt(np.mean(diff * diff)) / np.sqrt(np.mean(want * want))),
+            "mass_drift_rel": float(abs(m1 - m0) / m0), "min_psi": float(got.min()),
+            "against": "the CPU oracle (FP64) from the same (FP32-representable) start"}
 
 
 def time_adjoint(mp, torch, dev, steps=20, checkpoint_every=5, reps=3):
@@ -250,6 +341,8 @@ def main():
                     help="skip the adjoint/forward timing on the 256x128x60 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain device copy of one field (for counter calibration)")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 leg of the default FP64 run")
     ap.add_argument("--no-unstructured", action="store_true",
                     help="skip the edge-based step on the octahedral grid")
     ap.add_argument("--graph", action="store_true",
@@ -271,60 +364,30 @@ def main():
     mp.lib()  # fail loudly if the HIP library is missing
 
     w = make_workload(args.workload, args.dtype)
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
     elem = 8 if args.dtype == "f64" else 4
     log(f"[bench] workload {w.name} shape={w.shape} iters={w.iters} limiter={w.limiter} dtype={args.dtype}")
     dev = torch.device("cuda:0")
-    psi = torch.from_numpy(w.psi).to(dev, tdt)
-    cx, cy, cz, g = (torch.from_numpy(a).to(dev, tdt) for a in (w.cx, w.cy, w.cz, w.g))
-    p = mp.problem_for(w.shape, w.bc, w.iters, w.limiter, args.dtype)
-    ws = torch.empty(mp.workspace_bytes(p, mp.MPDATA_OP_RUN), dtype=torch.uint8, device=dev)
-    kw = dict(iters=w.iters, limiter=w.limiter, bc=w.bc, workspace=ws)
-
-    stream = torch.cuda.current_stream(dev)
-    if args.warmup:
-        mp.run(psi, cx, cy, cz, g, args.warmup, **kw)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} steps done")
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    graph = None
-    if args.graph:
-        # the K steps captured once on a side stream, then replayed
-        side = torch.cuda.Stream(dev)
-        side.wait_stream(stream)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(side):
-            with torch.cuda.graph(graph, stream=side):
-                mp.run(psi, cx, cy, cz, g, args.steps, **kw)
-        stream.wait_stream(side)
-        graph.replay()               # one untimed replay
-        torch.cuda.synchronize()
-        log(f"[bench] captured {args.steps} steps in one graph")
-    torch.cuda.synchronize()
-    mp.timing_enable(True)          # HIP events around every kernel launch, on the launch stream
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    if graph is not None:
-        graph.replay()
-    else:
-        mp.run(psi, cx, cy, cz, g, args.steps, **kw)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    mp.timing_enable(False)
-    ev_ms = ev0.elapsed_time(ev1)
-    pass_ms, pass_n = mp.timing_read(mp.MPDATA_KERNEL_PASS)
-    donor_ms, donor_n = mp.timing_read(mp.MPDATA_KERNEL_DONOR)
-    stage_ms, stage_n = mp.timing_read(mp.MPDATA_KERNEL_STAGE)
-    log(f"[bench] {args.steps} steps: wall {wall*1e3:.2f} ms, events {ev_ms:.2f} ms; "
-        f"pass kernel {pass_n} x {pass_ms / max(pass_n, 1):.1f} ms, donor {donor_n} x "
-        f"{donor_ms / max(donor_n, 1):.1f} ms")
-
+    fw = time_forward(mp, torch, dev, w, args.dtype, args.steps, args.warmup, args.graph)
+    wall, ev_ms = fw["wall"], fw["ev_ms"]
+    pass_ms, pass_n, donor_ms, donor_n = fw["pass_ms"], fw["pass_n"], fw["donor_ms"], fw["donor_n"]
     ms_per_step = wall * 1e3 / args.steps
     updates = w.cells * args.steps / wall
-    roof, alu = roofline(w, elem, args.dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, args.steps)
+    roof, pass_model, alu = roofline(w, elem, args.dtype, pass_ms, pass_n, fw["stage_ms"], fw["stage_n"], ev_ms,
+                                     args.steps)
+
+    # the FP32 leg of the same workload (inputs already FP32-representable)
+    fp32 = None
+    if args.dtype == "f64" and not args.no_fp32:
+        f3 = time_forward(mp, torch, dev, w, "f32", args.steps, args.warmup, args.graph)
+        r32, m32, _ = roofline(w, 4, "f32", f3["pass_ms"], f3["pass_n"], f3["stage_ms"], f3["stage_n"], f3["ev_ms"],
+                               args.steps)
+        fp32 = {"value": round(w.cells * args.steps / f3["wall"], 1), "unit": "grid-point updates/s",
+                "ms_per_step": round(f3["wall"] * 1e3 / args.steps, 4),
+                "ms_per_step_events": round(f3["ev_ms"] / args.steps, 4),
+                "roofline": r32, "roofline_pass_model": m32,
+                "pass_launches": f3["pass_n"], "pass_ms_avg": round(f3["pass_ms"] / max(f3["pass_n"], 1), 4),
+                "donor_launches": f3["donor_n"], "donor_ms_avg": round(f3["donor_ms"] / max(f3["donor_n"], 1), 4),
+                "speedup_vs_f64": round(wall / f3["wall"], 3)}
 
     adjoint = None
     if not args.no_adjoint and args.dtype == "f64":
@@ -337,6 +400,8 @@ def main():
         unstructured = time_unstructured(mp, torch, dev, cpu=not args.no_cpu_baseline)
 
     # practical HBM ceiling: a plain device copy of one field, read + write
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    stream = torch.cuda.current_stream(dev)
     csrc = torch.empty(w.cells, dtype=tdt, device=dev).fill_(1.0)
     cdst = torch.empty_like(csrc)
     cdst.copy_(csrc)
@@ -402,17 +467,11 @@ def main():
                              "sample": f"1 step of levels 0-{nz1 - 1} of {w.name}, {one_s:.2f} s"}
         log(f"[bench] cpu oracle, 1 thread: {cells1} cells in {one_s:.2f} s")
         # the same n steps on the GPU from the same start: errors against the oracle
-        x = torch.from_numpy(w.psi).to(dev, tdt)
-        m0 = mp.mass(x, g, bc=w.bc)
-        mp.run(x, cx, cy, cz, g, n, **kw)
-        m1 = mp.mass(x, g, bc=w.bc)
-        got = x.double().cpu().numpy()
-        diff = got - out
-        accuracy = {"steps": n, "max_abs_err_rel": float(np.max(np.abs(diff)) / np.max(np.abs(out))),
-                    "rms_err_rel": float(np.sqrt(np.mean(diff * diff)) / np.sqrt(np.mean(out * out))),
-                    "mass_drift_rel": float(abs(m1 - m0) / m0), "min_psi": float(got.min()),
-                    "against": "the CPU oracle (FP64) from the same start"}
-        log(f"[bench] accuracy after {n} steps: {accuracy}")
+        accuracy = gpu_accuracy(mp, torch, dev, w, args.dtype, n, out)
+        log(f"[bench] accuracy ({args.dtype}) after {n} steps: {accuracy}")
+        if fp32 is not None:
+            fp32["accuracy"] = gpu_accuracy(mp, torch, dev, w, "f32", n, out)
+            log(f"[bench] accuracy (f32) after {n} steps: {fp32['accuracy']}")
 
     line = {
         "metric": METRIC,
@@ -430,10 +489,11 @@ def main():
         "config": {"workload": w.name, "nx": w.shape[2], "ny": w.shape[1], "nz": w.shape[0],
                    "iters": w.iters, "limiter": w.limiter, "bc": list(w.bc), "parallelism": "single-gpu"},
         "roofline": roof,
+        "roofline_pass_model": pass_model,
         "roofline_alu": alu,
+        "fp32": fp32,
         "step": {"ms_per_step_events": round(ev_ms / args.steps, 4),
-                 "hbm_frac_step": round(bytes_per_cell_step(elem) * w.cells * args.steps / (ev_ms * 1e-3)
-                                        / 1e9 / HBM_PEAK_GBS, 4),
+                 "hbm_frac_step": roof["step_frac"],
                  "pass_launches": pass_n, "pass_ms_avg": round(pass_ms / max(pass_n, 1), 4),
                  "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
         "cpu_baseline": cpu,
@@ -441,7 +501,7 @@ def main():
         "hbm_copy": {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
                      "pass_frac_of_copy": round(roof["achieved"] / copy_gbs, 4),
                      "what": "torch device copy of one field (read + write), median of 5"},
-        "graph": bool(graph is not None),
+        "graph": fw["graph"],
         "adjoint": adjoint,
         "batched": batched,
         "unstructured": unstructured,

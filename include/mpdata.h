@@ -19,13 +19,26 @@
  * (i+1/2, j, k), cy on (i, j+1/2, k), cz on (i, j, k+1/2).  On a periodic axis
  * the last slot is the wrap face n-1/2 == -1/2.  On a closed axis the faces
  * -1/2 and n-1/2 carry no flux and the slot n-1 is never read.  g is the
- * metric (cell volume factor, the paper's dual volume times density) and must
- * be > 0.  psi must be >= 0 (the sign-preserving form of the scheme); this is
- * a precondition and is not checked.
+ * metric (cell volume factor, the paper's dual volume times density).
+ *
+ * Input ranges (preconditions, not checked unless MPDATA_DEBUG is set):
+ *   psi in [0, 1e100] in FP64, [0, 1e30] in FP32 (the sign-preserving form of
+ *       the scheme needs psi >= 0; the upper bound keeps the fused pass's
+ *       products of three guarded pair sums finite);
+ *   g in [1e-6, 1e6];
+ *   |Courant numbers| small enough for the donor-cell bound (the outflow
+ *       Courant sum of a cell over its g at most 1) for positivity.
+ * Within these ranges (and eps as below) every result is finite.
+ *
+ * MPDATA_DEBUG.  With the environment variable MPDATA_DEBUG set (to anything
+ * but "0"), mpdata_step, mpdata_run, mpdata_adjoint and mpdata_run_batched
+ * scan psi and g on the device before enqueueing the step and return
+ * MPDATA_EINVAL if a value lies outside the ranges above or is NaN.  The scan
+ * synchronises the stream; it is skipped while the stream is being captured.
  *
  * Ownership.  The caller owns every buffer, including the workspace, whose
  * size mpdata_workspace_bytes() returns.  These calls never allocate device
- * memory.  psi_in must not alias psi_out.
+ * memory.  psi_in must not alias psi_out (MPDATA_EINVAL).
  *
  * Errors.  Every call validates its arguments synchronously, before anything
  * is enqueued, and returns MPDATA_OK or a negative code; the reason is then
@@ -50,8 +63,10 @@ extern "C" {
 
 enum {
     MPDATA_OK = 0,
-    MPDATA_EINVAL = -1,       /* invalid argument, see mpdata_last_error()   */
-    MPDATA_ENOMEM = -2,       /* workspace too small                          */
+    MPDATA_EINVAL = -1,       /* invalid argument (a workspace below the size */
+                              /* the query returns included), see             */
+                              /* mpdata_last_error()                          */
+    MPDATA_ENOMEM = -2,       /* reserved; not returned by these calls        */
     MPDATA_EDEVICE = -3,      /* HIP launch or runtime error                  */
     MPDATA_EUNSUPPORTED = -4  /* valid but not implemented combination        */
 };
@@ -69,7 +84,9 @@ typedef struct {
     int32_t dtype;        /* MPDATA_F64 or MPDATA_F32 (storage and arithmetic)    */
     int32_t reserved;     /* must be 0                                            */
     double eps;           /* denominator guard of the antidiffusive and limiter   */
-                          /* ratios; 0 selects 1e-15                              */
+                          /* ratios: 0 selects 1e-15, else in [1e-30, 1e-3]      */
+                          /* (the floor keeps every guarded denominator normal   */
+                          /* in both precisions)                                 */
 } mpdata_problem;
 
 /* Workspace bytes for `op` (MPDATA_OP_*).  nsteps and checkpoint_every matter
@@ -105,7 +122,9 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
  * min(1, min(a, b)) to its first minimal entry, the limiter bounds to their
  * first extremal entry).  psiT_out (nullable) receives psi_T.  No atomics:
  * the result is bitwise reproducible.  ws: at least the MPDATA_OP_ADJOINT
- * size for the same nsteps and checkpoint_every.  The MPDATA iterations and
+ * size for the same nsteps and checkpoint_every.  No output (dJ_dpsi0,
+ * dJ_dc*, psiT_out) may alias an input, another output or the workspace
+ * (MPDATA_EINVAL).  The MPDATA iterations and
  * limiter this differentiates are those of mpdata_step (paper, Section 5,
  * and the scheme's literature); the paper itself has no adjoint. */
 int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_every,

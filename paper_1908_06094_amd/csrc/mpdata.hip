@@ -50,6 +50,13 @@ int ok()
 
 constexpr long long kMaxCells = 1LL << 34;   // 17 G cells: far beyond one GPU's HBM in FP32
 constexpr int kMaxIters = 8;
+constexpr double kEpsMin = 1e-30, kEpsMax = 1e-3;
+// Input ranges the kernels are exact within (checked under MPDATA_DEBUG):
+// psi in [0, kPsiMax], G in [kGMin, kGMax].  In FP64 the largest product the
+// fused pass forms is G_sum * (2 psi + eps)^3 <= 2e6 * 8e300, below the
+// FP64 maximum; in FP32 pair sums of psi stay below the FP32 maximum.
+constexpr double kPsiMax64 = 1e100, kPsiMax32 = 1e30;
+constexpr double kGMin = 1e-6, kGMax = 1e6;
 
 int validate(const mpdata_problem* p)
 {
@@ -73,7 +80,13 @@ int validate(const mpdata_problem* p)
     if (p->dtype != MPDATA_F64 && p->dtype != MPDATA_F32)
         return fail(MPDATA_EINVAL, "dtype=%d is neither MPDATA_F64 nor MPDATA_F32", p->dtype);
     if (p->reserved != 0) return fail(MPDATA_EINVAL, "reserved field must be 0");
-    if (!(p->eps >= 0.0) || p->eps > 1e-3) return fail(MPDATA_EINVAL, "eps=%g outside [0, 1e-3]", p->eps);
+    // eps = 0 selects the default; otherwise [kEpsMin, kEpsMax].  The floor
+    // keeps every guarded denominator a normal number in both precisions:
+    // the FP64 pass divides once over G_sum * d0 * d1 * d2 with each d >= eps
+    // (>= 2e-90 * G_min at the floor), beta over (in + eps)(out + eps), and
+    // FP32 takes eps as a float.
+    if (!(p->eps == 0.0 || (p->eps >= kEpsMin && p->eps <= kEpsMax)))
+        return fail(MPDATA_EINVAL, "eps=%g is neither 0 (the default) nor in [%g, %g]", p->eps, kEpsMin, kEpsMax);
     return MPDATA_OK;
 }
 
@@ -131,6 +144,64 @@ int launch_status(const char* what)
 {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MPDATA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return MPDATA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// MPDATA_DEBUG (environment variable, any value but "0"): the calls scan
+// their input tracer and metric on the device and refuse values outside the
+// documented ranges (psi in [0, psi_max], G in [kGMin, kGMax], NaN in either)
+// with MPDATA_EINVAL.  The scan synchronises the stream, so it is skipped
+// while the stream is being captured into a graph.
+// ---------------------------------------------------------------------------
+
+bool debug_on()
+{
+    const char* e = getenv("MPDATA_DEBUG");
+    return e && *e && strcmp(e, "0") != 0;
+}
+
+// flag = 1 where any of the n values lies outside [lo, hi] or is NaN (every
+// writer stores the same value, so the unordered stores are benign)
+template <class T>
+__global__ void __launch_bounds__(256) k_range_check(const T* __restrict__ a, long long n, double lo, double hi,
+                                                     unsigned* __restrict__ flag)
+{
+    bool bad = false;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const double x = (double)a[q];
+        bad |= !(x >= lo && x <= hi);
+    }
+    if (bad) *flag = 1u;
+}
+
+// Scans `count` tracer fields of n cells each at psi (consecutive) and the
+// metric g; flag: 8 bytes of device scratch.
+int debug_check(int dtype, long long n, int count, const void* psi, const void* g, void* flag, hipStream_t st,
+                const char* who)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return MPDATA_OK;
+    unsigned* f = (unsigned*)flag;
+    const double psi_max = dtype == MPDATA_F64 ? kPsiMax64 : kPsiMax32;
+    mpdata::k_fill<unsigned><<<1, 64, 0, st>>>(f, 2, 0u);
+    const long long np = n * count;
+    if (dtype == MPDATA_F64) {
+        k_range_check<double><<<1024, 256, 0, st>>>((const double*)psi, np, 0.0, psi_max, f);
+        k_range_check<double><<<1024, 256, 0, st>>>((const double*)g, n, kGMin, kGMax, f + 1);
+    } else {
+        k_range_check<float><<<1024, 256, 0, st>>>((const float*)psi, np, 0.0, psi_max, f);
+        k_range_check<float><<<1024, 256, 0, st>>>((const float*)g, n, kGMin, kGMax, f + 1);
+    }
+    if (int rc = launch_status("MPDATA_DEBUG range check")) return rc;
+    unsigned h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, f, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MPDATA_EDEVICE, "MPDATA_DEBUG range check: %s", hipGetErrorString(e));
+    if (h[0])
+        return fail(MPDATA_EINVAL, "MPDATA_DEBUG: %s: psi holds values outside [0, %g] or NaN", who, psi_max);
+    if (h[1]) return fail(MPDATA_EINVAL, "MPDATA_DEBUG: %s: g holds values outside [%g, %g] or NaN", who, kGMin, kGMax);
     return MPDATA_OK;
 }
 
@@ -1065,7 +1136,7 @@ int mpdata_urun(const mpdata_umesh* m, int32_t nsteps, void* psi, const void* vn
     if (nsteps < 0) return fail(MPDATA_EINVAL, "nsteps=%d is negative", nsteps);
     if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
     const size_t need = mpdata_uworkspace_bytes(m);
-    if (ws_bytes < need) return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
+    if (ws_bytes < need) return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
     hipStream_t st = (hipStream_t)stream;
     void* cur = psi;
     for (int s = 0; s < nsteps; ++s) {
@@ -1145,7 +1216,9 @@ int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out, cons
     if (!ws) return fail(MPDATA_EINVAL, "workspace is NULL");
     if (!aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < step_bytes(p))
-        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the step needs", ws_bytes, step_bytes(p));
+        return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the step needs", ws_bytes, step_bytes(p));
+    if (debug_on())
+        if (int rc = debug_check(p->dtype, cells(p), 1, psi_in, g, ws, (hipStream_t)stream, "mpdata_step")) return rc;
     return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -1163,9 +1236,11 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* c
     if (!aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace must be 256-byte aligned");
     size_t need = step_bytes(p) + field_bytes(p);
     if (ws_bytes < need)
-        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
+        return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the run needs", ws_bytes, need);
     if (nsteps == 0) return ok();
     hipStream_t st = (hipStream_t)stream;
+    if (debug_on())
+        if (int rc = debug_check(p->dtype, cells(p), 1, psi, g, ws, st, "mpdata_run")) return rc;
     void* alt = (char*)ws + step_bytes(p);
     void* cur = psi;
     for (int s = 0; s < nsteps; ++s) {
@@ -1196,14 +1271,34 @@ int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_e
     if (cz && !aligned(cz, 8)) return fail(MPDATA_EINVAL, "cz is not aligned to its element size");
     if (dJ_dcz && !aligned(dJ_dcz, 8)) return fail(MPDATA_EINVAL, "dJ_dcz is not aligned to its element size");
     if (psiT_out && !aligned(psiT_out, 8)) return fail(MPDATA_EINVAL, "psiT_out is not aligned");
-    if (dJ_dpsi0 == psi0 || dJ_dpsi0 == dJ_dpsiT)
-        return fail(MPDATA_EINVAL, "dJ_dpsi0 must not alias psi0 or dJ_dpsiT");
+    {
+        // no output may alias an input or another output: the sweep writes its
+        // outputs while it still reads the inputs (the seed is copied, the
+        // wind gradients are cleared, before the segments are recomputed)
+        const void* in[] = {psi0, cx, cy, cz, g, dJ_dpsiT};
+        const char* in_names[] = {"psi0", "cx", "cy", "cz", "g", "dJ_dpsiT"};
+        const void* out[] = {dJ_dpsi0, dJ_dcx, dJ_dcy, dJ_dcz, psiT_out};
+        const char* out_names[] = {"dJ_dpsi0", "dJ_dcx", "dJ_dcy", "dJ_dcz", "psiT_out"};
+        for (int o = 0; o < 5; ++o) {
+            if (!out[o]) continue;
+            for (int i = 0; i < 6; ++i)
+                if (out[o] == in[i])
+                    return fail(MPDATA_EINVAL, "%s must not alias the input %s", out_names[o], in_names[i]);
+            for (int o2 = 0; o2 < o; ++o2)
+                if (out[o] == out[o2])
+                    return fail(MPDATA_EINVAL, "%s must not alias the output %s", out_names[o], out_names[o2]);
+            if (out[o] == ws) return fail(MPDATA_EINVAL, "%s must not alias the workspace", out_names[o]);
+        }
+    }
     if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
     const int K = checkpoint_every > 0 ? checkpoint_every : (nsteps > 0 ? nsteps : 1);
     const AdjLayout L = adj_layout(p, nsteps, K);
     if (ws_bytes < L.fields * L.fb)
-        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the adjoint needs", ws_bytes,
+        return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the adjoint needs", ws_bytes,
                     L.fields * L.fb);
+    if (debug_on())
+        if (int rc = debug_check(p->dtype, cells(p), 1, psi0, g, ws, (hipStream_t)stream, "mpdata_adjoint"))
+            return rc;
     return adjoint_run(p, nsteps, K, (const double*)psi0, (const double*)cx, (const double*)cy, (const double*)cz,
                        (const double*)g, (const double*)dJ_dpsiT, (double*)dJ_dpsi0, (double*)dJ_dcx,
                        (double*)dJ_dcy, (double*)dJ_dcz, (double*)psiT_out, ws, (hipStream_t)stream);
@@ -1233,8 +1328,17 @@ int mpdata_run_batched(const mpdata_problem* common, int32_t nitems, const mpdat
     if (!ws || !aligned(ws, 256)) return fail(MPDATA_EINVAL, "workspace is NULL or not 256-byte aligned");
     const batch::Layout L = batch::layout(&c, nitems, items);
     if (ws_bytes < L.total)
-        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the batch needs", ws_bytes, L.total);
+        return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the batch needs", ws_bytes, L.total);
     if (nsteps == 0) return ok();
+    if (debug_on())
+        for (int i = 0; i < nitems; ++i) {
+            char who[64];
+            snprintf(who, sizeof who, "mpdata_run_batched item %d", i);
+            const long long n = (long long)items[i].nx * items[i].ny * items[i].nz;
+            if (int rc = debug_check(c.dtype, n, items[i].ntracers, items[i].psi, items[i].g, ws, (hipStream_t)stream,
+                                     who))
+                return rc;
+        }
     if (c.dtype == MPDATA_F64) return run_batched<double>(&c, nitems, items, nsteps, flags, ws, (hipStream_t)stream);
     return run_batched<float>(&c, nitems, items, nsteps, flags, ws, (hipStream_t)stream);
 }
@@ -1248,7 +1352,7 @@ int mpdata_mass(const mpdata_problem* p, const void* psi, const void* g, double*
     if (!host_out) return fail(MPDATA_EINVAL, "host_out is NULL");
     if (!ws || !aligned(ws, 8)) return fail(MPDATA_EINVAL, "workspace is NULL or misaligned");
     if (ws_bytes < kMassBytes)
-        return fail(MPDATA_ENOMEM, "workspace of %zu bytes is below the %zu the mass needs", ws_bytes, kMassBytes);
+        return fail(MPDATA_EINVAL, "workspace of %zu bytes is below the %zu the mass needs", ws_bytes, kMassBytes);
     hipStream_t st = (hipStream_t)stream;
     double* part = (double*)ws;
     if (p->dtype == MPDATA_F64)

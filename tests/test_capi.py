@@ -83,7 +83,7 @@ def test_pointer_and_workspace_checks():
     assert _call_step(mp, p, ws=128) == mp._lib.MPDATA_EINVAL                       # ws alignment
     need = mp.workspace_bytes(p, mp.MPDATA_OP_STEP)
     assert need > 0
-    assert _call_step(mp, p, ws_bytes=need - 1) == mp._lib.MPDATA_ENOMEM
+    assert _call_step(mp, p, ws_bytes=need - 1) == mp._lib.MPDATA_EINVAL
     lib = mp.lib()
     _no_device()
     assert lib.mpdata_run(ctypes.byref(p), -1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
@@ -158,7 +158,7 @@ def test_unstructured_validation():
     assert b"alias" in lib.mpdata_last_error()
     assert lib.mpdata_ustep(ctypes.byref(m), v(512), v(2048), None, None, v(1024), None) == mp._lib.MPDATA_EINVAL
     assert lib.mpdata_urun(ctypes.byref(m), 2, v(512), v(768), None, v(1024), v(4096), 16, None) == \
-        mp._lib.MPDATA_ENOMEM
+        mp._lib.MPDATA_EINVAL
 
 
 def test_unsupported_combinations():
@@ -176,3 +176,42 @@ def test_unsupported_combinations():
     arr = _items(mp, [(64, 32, 20, 1)])
     assert lib.mpdata_run_batched(ctypes.byref(p), 1, ctypes.cast(arr, ctypes.c_void_p), 2, 0, v(4096), 1 << 40,
                                   None) in (mp._lib.MPDATA_EUNSUPPORTED, mp._lib.MPDATA_EINVAL)
+
+
+def test_eps_floor():
+    """eps is 0 (the default) or in [1e-30, 1e-3]: below the floor a guarded
+    denominator could leave the normal range."""
+    mp = _mp()
+    lib = mp.lib()
+    for eps, ok in ((0.0, True), (1e-30, True), (1e-15, True), (1e-3, True), (9e-31, False), (1e-100, False),
+                    (2e-3, False), (float("nan"), False), (-1e-15, False)):
+        p = mp.problem_for((4, 5, 6), eps=eps)
+        assert (lib.mpdata_workspace_bytes(ctypes.byref(p), 0, 0, 0) > 0) == ok, eps
+        if not ok:
+            assert b"eps" in lib.mpdata_last_error()
+
+
+
+
+
+def test_adjoint_rejects_aliased_outputs():
+    """No adjoint output may alias an input, another output or the workspace."""
+    mp = _mp()
+    lib = mp.lib()
+    _no_device()
+    v = ctypes.c_void_p
+    p = mp.problem_for((4, 5, 6))
+    psi0, cx, cy, cz, g, seed = 1 << 12, 2 << 12, 3 << 12, 4 << 12, 5 << 12, 6 << 12
+    d0, dx, dy, dz, pt, ws = 7 << 12, 8 << 12, 9 << 12, 10 << 12, 11 << 12, 1 << 20
+
+    def call(**kw):
+        a = dict(psi0=psi0, cx=cx, cy=cy, cz=cz, g=g, seed=seed, d0=d0, dx=dx, dy=dy, dz=dz, pt=pt)
+        a.update(kw)
+        return lib.mpdata_adjoint(ctypes.byref(p), 2, 1, v(a["psi0"]), v(a["cx"]), v(a["cy"]), v(a["cz"]),
+                                  v(a["g"]), v(a["seed"]), v(a["d0"]), v(a["dx"]), v(a["dy"]), v(a["dz"]),
+                                  v(a["pt"]), v(ws), 1 << 40, None)
+
+    for kw in (dict(pt=seed), dict(dx=cx), dict(dy=cy), dict(dz=cz), dict(d0=psi0), dict(d0=seed), dict(dy=dx),
+               dict(pt=d0), dict(dz=g), dict(pt=ws)):
+        assert call(**kw) == mp._lib.MPDATA_EINVAL, kw
+        assert b"alias" in lib.mpdata_last_error()

@@ -228,7 +228,9 @@ def test_fp32_matches_fp64_oracle(shape, bc, iters, lim, kernels):
     mp.run(t, *[_dev(a, torch.float32) for a in (cx, cy, cz, g)], 10, iters=iters, limiter=lim, bc=bc)
     torch.cuda.synchronize()
     got = t.double().cpu().numpy()
-    assert _rel(got, want) <= TOL32
+    err = _rel(got, want)
+    _say(f"[parity-f32]   rel err {err:.3e}")
+    assert err <= TOL32
     if lim:
         assert got.min() >= 0.0
 
@@ -248,7 +250,9 @@ def test_fp32_latlon_1024x512x80_full_size():
     mp.run(t, *args, 2, iters=w.iters, limiter=w.limiter, bc=w.bc)
     torch.cuda.synchronize()
     got = t.double().cpu().numpy()
-    assert _rel(got, want) <= TOL32
+    err = _rel(got, want)
+    _say(f"[parity-f32]   rel err {err:.3e}")
+    assert err <= TOL32
     assert got.min() >= 0.0
     assert abs(mp.mass(t, args[3]) - m0) <= 1e-6 * m0
 

@@ -406,3 +406,23 @@ def test_invalid_arguments_rejected():
         oracle.step(oracle.RefProblem(2, 2, 2, iters=0), a, a, a, a, a)
     with pytest.raises(ValueError):
         oracle.step(oracle.RefProblem(0, 2, 2), np.ones((2, 2, 0)), *(np.ones((2, 2, 0)),) * 4)
+
+
+# ---------------------------------------------------------------------------
+# Failure propagation: a NaN in the input is not silently lost
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("iters,limiter", [(1, False), (3, False), (3, True)])
+def test_nan_in_input_reaches_its_cell(iters, limiter):
+    """A NaN planted in psi^n stays in its own cell after a step (the update
+    psi - div/G carries it) and after a run, whatever the max/min of the
+    limiter do with it; cells outside its stencil stay finite."""
+    shape, bc = (14, 9, 12), (P, C, C)
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=8, courant=0.8)
+    psi[2, 4, 6] = np.nan
+    p = oracle.RefProblem(shape[2], shape[1], shape[0], bc=bc, iters=iters, limiter=limiter)
+    out = oracle.step(p, psi, cx, cy, cz, g)
+    assert np.isnan(out[2, 4, 6])
+    # 11 levels away: beyond one step's vertical reach (1 for the donor pass, 2 per corrective pass)
+    assert np.all(np.isfinite(out[13]))
+    assert np.isnan(oracle.run(p, 3, psi, cx, cy, cz, g)[2, 4, 6])
