@@ -101,6 +101,23 @@ int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out,
                 const void* cx, const void* cy, const void* cz, const void* g,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the step
+ * of mpdata_step, with its workspace taken from a fixed device array of
+ * MPDATA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends, instead of a caller's buffer.  The call
+ * allocates no device memory (its first call on a device looks the array's
+ * address up).  A problem whose MPDATA_OP_STEP workspace exceeds the array
+ * (FP64: up to ~2.1 M cells, e.g. 256 x 128 x 64; FP32: twice that) is
+ * refused with MPDATA_EINVAL.  All calls on one GPU share that GPU's array
+ * and leave their intermediates in it: calls that overlap on one GPU (on
+ * concurrent streams or from several threads) race and their results are
+ * undefined, so the caller serialises them.  Arguments, errors and
+ * asynchrony as mpdata_step. */
+#define MPDATA_NOALLOC_SCRATCH_BYTES (168u << 20)
+int mpdata_step_noalloc(const mpdata_problem* p, const void* psi_in, void* psi_out, const void* cx,
+                        const void* cy, const void* cz, const void* g, void* stream);
+
 /* nsteps >= 0 steps in place: psi holds psi^0 on entry and psi^nsteps on
  * return (after the stream has run).  Winds and metric are the same for all
  * steps.  ws: at least the MPDATA_OP_RUN size. */

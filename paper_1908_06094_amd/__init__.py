@@ -43,6 +43,8 @@ from ._lib import (  # noqa: F401
     problem_for,
     run,
     step,
+    step_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     timing_enable,
     timing_read,
     workspace_bytes,

@@ -45,6 +45,7 @@ _SIGNATURES = {
     "mpdata_workspace_bytes": ([_pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
     "mpdata_step": ([_pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_run": ([_pp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "mpdata_step_noalloc": ([_pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "mpdata_mass": ([_pp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "mpdata_adjoint": ([_pp, ctypes.c_int32, ctypes.c_int32] + [_vp] * 11 + [_vp, ctypes.c_size_t, _vp],
                        ctypes.c_int),
@@ -160,6 +161,19 @@ def step(psi, cx, cy, cz, g, *, iters=2, limiter=True, bc=("periodic", "closed",
     ws = workspace if workspace is not None else _workspace(nb, psi.device)
     _check(lib().mpdata_step(ctypes.byref(p), _ptr(psi), _ptr(out), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
                              _ptr(ws), ws.numel(), ctypes.c_void_p(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 168 << 20   # MPDATA_NOALLOC_SCRATCH_BYTES
+
+
+def step_noalloc(psi, cx, cy, cz, g, out, *, iters=2, limiter=True, bc=("periodic", "closed", "closed"), eps=0.0):
+    """One MPDATA step into `out` through mpdata_step_noalloc (the library's
+    fixed device scratch, no workspace): allocates nothing."""
+    stream = _fields(psi, (cx, cy, cz, g, out))
+    p = problem_for(tuple(psi.shape), bc, iters, limiter, _dtype_code(psi), eps)
+    _check(lib().mpdata_step_noalloc(ctypes.byref(p), _ptr(psi), _ptr(out), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(g),
+                                     ctypes.c_void_p(stream)))
     return out
 
 

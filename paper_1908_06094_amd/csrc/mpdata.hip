@@ -1106,6 +1106,43 @@ int validate_ucall(const mpdata_umesh* m, const void* psi, const void* vn, const
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free step (mpdata_step_noalloc): the step's
+// workspace as a device array of the code object, one copy per GPU the
+// library runs on, held until the process ends.  In host code `scratch`
+// names a host-side stand-in: its device address on the current GPU comes
+// from hipGetSymbolAddress, taken once per device and kept in
+// g_scratch_addr; only that address is ever handed to a kernel.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[MPDATA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {nullptr};
+
+// The current device's scratch address (looked up on its first use).
+int scratch_address(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(MPDATA_EDEVICE, "mpdata_step_noalloc: no current device (or device index >= 64)");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MPDATA_EDEVICE, "mpdata_step_noalloc: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return MPDATA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Exported entry points
 // ---------------------------------------------------------------------------
 
@@ -1220,6 +1257,30 @@ int mpdata_step(const mpdata_problem* p, const void* psi_in, void* psi_out, cons
     if (debug_on())
         if (int rc = debug_check(p->dtype, cells(p), 1, psi_in, g, ws, (hipStream_t)stream, "mpdata_step")) return rc;
     return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int mpdata_step_noalloc(const mpdata_problem* p, const void* psi_in, void* psi_out, const void* cx, const void* cy,
+                        const void* cz, const void* g, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (int rc = check_ptr(psi_in, "psi_in", p)) return rc;
+    if (int rc = check_ptr(psi_out, "psi_out", p)) return rc;
+    if (int rc = check_ptr(cx, "cx", p)) return rc;
+    if (int rc = check_ptr(cy, "cy", p)) return rc;
+    if (cz && !aligned(cz, elem_size(p))) return fail(MPDATA_EINVAL, "cz is not aligned to its element size");
+    if (int rc = check_ptr(g, "g", p)) return rc;
+    if (psi_in == psi_out) return fail(MPDATA_EINVAL, "psi_in must not alias psi_out");
+    const size_t need = step_bytes(p);
+    if (need > (size_t)MPDATA_NOALLOC_SCRATCH_BYTES)
+        return fail(MPDATA_EINVAL, "mpdata_step_noalloc: the step needs %zu bytes of workspace, above the %zu of "
+                    "the fixed scratch (use mpdata_step with a workspace of that size)",
+                    need, (size_t)MPDATA_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    if (debug_on())
+        if (int rc = debug_check(p->dtype, cells(p), 1, psi_in, g, ws, (hipStream_t)stream, "mpdata_step_noalloc"))
+            return rc;
+    return dispatch_step(p, psi_in, psi_out, cx, cy, cz, g, ws, need, (hipStream_t)stream);
 }
 
 int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi, const void* cx, const void* cy, const void* cz,

@@ -191,7 +191,23 @@ def test_eps_floor():
             assert b"eps" in lib.mpdata_last_error()
 
 
-
+def test_noalloc_refuses_grids_beyond_its_scratch():
+    """mpdata_step_noalloc checks its fixed scratch's size before it touches
+    the device."""
+    mp = _mp()
+    lib = mp.lib()
+    big = mp.problem_for((80, 256, 256))
+    assert mp.workspace_bytes(big, mp.MPDATA_OP_STEP) > mp.NOALLOC_SCRATCH_BYTES
+    small = mp.problem_for((60, 128, 256))
+    assert mp.workspace_bytes(small, mp.MPDATA_OP_STEP) <= mp.NOALLOC_SCRATCH_BYTES
+    _no_device()
+    v = ctypes.c_void_p
+    assert lib.mpdata_step_noalloc(ctypes.byref(big), v(256), v(512), v(768), v(1024), None, v(1280), None) == \
+        mp._lib.MPDATA_EINVAL
+    assert b"scratch" in lib.mpdata_last_error()
+    assert lib.mpdata_step_noalloc(ctypes.byref(small), v(256), v(256), v(768), v(1024), None, v(1280), None) == \
+        mp._lib.MPDATA_EINVAL
+    assert b"alias" in lib.mpdata_last_error()
 
 
 def test_adjoint_rejects_aliased_outputs():
