@@ -208,9 +208,14 @@ def test_latlon_1024x512x80_full_size_one_step():
 # ---------------------------------------------------------------------------
 
 # FP32 tolerance: the inputs are FP32-representable, so the error is the FP32
-# rounding of ~250 operations per pass accumulated over the steps; relative to
-# max|psi| it stays at a few hundred ulp of FP32 over 10 steps.
-TOL32 = 3e-5
+# rounding (unit 6e-8) of each pass accumulated over the steps.  Measured
+# over these cases (10 steps, printed by the test): 7.7e-8 .. 2.6e-7 relative
+# to max|psi|, on both kernel paths; the bound is at most 10x each case's
+# error, so a coarser arithmetic in any stage (an FP32 limiter ratio, a
+# reciprocal left unrefined) fails it.
+TOL32 = 7e-7
+# 2 steps of the 1024x512x80 workload: measured 8.6e-8
+TOL32_FULL = 8e-7
 
 
 @pytest.mark.parametrize("shape,bc,iters,lim", [CASES[0], CASES[1], CASES[2], CASES[4], CASES[6], CASES[8],
@@ -252,9 +257,10 @@ def test_fp32_latlon_1024x512x80_full_size():
     got = t.double().cpu().numpy()
     err = _rel(got, want)
     _say(f"[parity-f32]   rel err {err:.3e}")
-    assert err <= TOL32
+    assert err <= TOL32_FULL
     assert got.min() >= 0.0
-    assert abs(mp.mass(t, args[3]) - m0) <= 1e-6 * m0
+    # the mass sums are FP64: the drift is the FP32 rounding of the updates (measured 3.6e-11 over 5 steps)
+    assert abs(mp.mass(t, args[3]) - m0) <= 1e-9 * m0
 
 
 def test_run_captured_in_a_graph_matches_eager():
