@@ -77,6 +77,18 @@ struct Tile {
     // FP64 the 480-byte rows are not, and the tile layout measured slower)
     static constexpr bool tiled_velocities = sizeof(T) == 4;
     static_assert((1 << shift) == lanes && lanes >= 16 && lanes <= 64, "a tile row is 16, 32 or 64 lanes");
+    // The pass with the donor-cell pass folded in (DONOR).  FP64 widens its x
+    // halo to 3 (58 interior columns), so that psi^(1) is needed on lanes
+    // 1 .. 62 only and every donor-cell x flux comes from a lane shift: the
+    // row-end lanes then need no extra loads (their registers are what the
+    // 168-register budget lacks).  FP32 keeps the halo of 2 (its tile layout
+    // of the velocities handed to the next pass is the 28 x 20 interior) and
+    // loads the neighbours beyond the row ends; it runs one workgroup per
+    // CU, where its registers fit without spilling.
+    static constexpr int donor_halo_x = sizeof(T) == 8 ? 3 : 2;
+    static constexpr int donor_tile_x = lanes - 2 * donor_halo_x;
+    static constexpr int donor_wgs_per_cu = 1;
+    static constexpr int donor_waves_per_simd = donor_wgs_per_cu * kThreads / 256;
 };
 
 // ---------------------------------------------------------------------------
@@ -271,6 +283,16 @@ struct Slots {
     T fy[2][kRows][kLanes];
 };
 
+// The pass that also runs the donor-cell pass (DONOR) needs three more
+// plane slots: psi^n of the current plane and of the next (ring by plane
+// parity; the y neighbours of the donor-cell fluxes) and the donor-cell y
+// flux at each row's upper face, which the row above reads.
+template <class T>
+struct SlotsDonor : Slots<T> {
+    T psd[2][Tile<T>::rows][Tile<T>::lanes];
+    T fyd[Tile<T>::rows][Tile<T>::lanes];
+};
+
 // One column's values of one plane: the loaded fields and what is derived
 // from them.  Three banks hold the planes k-1, k and k+1.
 template <class T>
@@ -282,6 +304,9 @@ struct Bank {
 template <class T>
 struct Raw {
     T phi, psin, u, v, w, g;
+    // DONOR only: psi^n and Cx beyond the row's ends (lanes 0 and R-1), and
+    // psi^n and Cy beyond the tile's outer rows (rows 0 and R-1)
+    T xe, cxl, yx, cyd;
 };
 
 // March output planes [kb, ke) of one tile of one problem: the part of
@@ -295,12 +320,28 @@ struct Raw {
 //   ROLE 2: the outer halo rows (0 and R-1): their loads and LDS slots and,
 //           with the limiter, (row 0) the y-face velocity below row 1,
 //           which row 1's beta needs.
-template <class T, bool LIMIT, bool WRITE_VEL, int ROLE, bool REC>
-__device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
+// DONOR: the pass is the first corrective pass of a step and forms its input
+// iterate psi^(1) itself, by the donor-cell pass on psi^n with the Courant
+// numbers (a.u, a.v, a.w), plane by plane ahead of its use (a.phi is not
+// read).  psi^n is loaded one plane ahead of the other fields and published
+// to LDS for the y neighbours; an extra march phase and barrier exchange the
+// donor-cell y fluxes; the row-end lanes and the outer rows load their
+// neighbours beyond the tile.  Per cell the pass then reads psi^n, Cx, Cy,
+// Cz and G once: the step's separate donor-cell pass and its psi^(1) round
+// trip through HBM disappear.
+template <class T, bool LIMIT, bool WRITE_VEL, int ROLE, bool REC, bool DONOR, class SL>
+__device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, SL& S, const int tile,
                                           const int kb, const int ke)
 {
     constexpr int kLanes = Tile<T>::lanes, kRows = Tile<T>::rows;
-    constexpr int kTileX = Tile<T>::tile_x, kTileY = Tile<T>::tile_y;
+    constexpr int kTileY = Tile<T>::tile_y;
+    // x halo and interior width of this kernel (the donor-fused FP64 pass
+    // widens its x halo); the tile layout of handed-over velocities keeps the
+    // plain pass's interior
+    constexpr int kHX = DONOR ? Tile<T>::donor_halo_x : kHalo;
+    constexpr int kTileX = kLanes - 2 * kHX;
+    constexpr int kLayX = Tile<T>::tile_x;
+    constexpr bool kXEdgeLoads = DONOR && kHX == kHalo;   // row-end lanes load their outer neighbour
     const int lane = threadIdx.x & (kLanes - 1);
     const int row = threadIdx.x >> Tile<T>::shift;
     const int up = row < kRows - 1 ? row + 1 : row;     // clamped: the edge rows are halo
@@ -310,7 +351,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
     {
         const int tx = tile % a.tiles_x;
         const int ty = tile / a.tiles_x;
-        const int gi = tx * kTileX - kHalo + lane;       // virtual column of this lane
+        const int gi = tx * kTileX - kHX + lane;         // virtual column of this lane
         const int gj = ty * kTileY - kHalo + row;
         const int ci = map_index(gi, geo.nx, geo.closed_x);
         const int cj = map_index(gj, geo.ny, geo.closed_y);
@@ -318,29 +359,60 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
         const bool ywall = wall_face(gj, geo.ny, geo.closed_y);
         // a plane holds at most 2^30 cells (checked on the host): 32-bit offsets
         const unsigned col = (unsigned)(cj * (int)geo.sy + ci);
-        const bool writer = lane >= kHalo && lane < kLanes - kHalo && row >= kHalo && row < kRows - kHalo &&
+        const bool writer = lane >= kHX && lane < kLanes - kHX && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
-        // this lane's cell in the tile layout (a writer's cell lies in its own tile)
-        const int ttx = ci / kTileX, tty = cj / kTileY;
-        const unsigned tcol = (unsigned)((tty * a.tiles_x + ttx) * (kTileX * kTileY) +
-                                         (cj - tty * kTileY) * kTileX + (ci - ttx * kTileX));
-        const long long tplane = tiled_plane<T>(a.tiles_x, a.tiles_y);
+        // this lane's cell in the tile layout of the velocities (blocks of
+        // the plain pass's kLayX x kTileY interior)
+        const int lay_tiles_x = (geo.nx + kLayX - 1) / kLayX;
+        const int lay_tiles_y = (geo.ny + kTileY - 1) / kTileY;
+        const int ttx = ci / kLayX, tty = cj / kTileY;
+        const unsigned tcol = (unsigned)((tty * lay_tiles_x + ttx) * (kLayX * kTileY) +
+                                         (cj - tty * kTileY) * kLayX + (ci - ttx * kLayX));
+        const long long tplane = tiled_plane<T>(lay_tiles_x, lay_tiles_y);
 
         // plane loader: cell quantities through the halo rule.  Every load is
         // issued unconditionally and the wall masks are applied where the
         // plane is consumed (one march step later), so nothing waits for a
         // prefetch on the step that issues it.
         const bool has_w = a.w != nullptr;     // without w, g is loaded in its place and masked
+        // DONOR: the neighbours beyond the row's ends and the tile's outer rows
+        const bool x_lo = lane == 0, x_hi = lane == kLanes - 1;
+        const bool y_lo = row == 0, y_hi = row == kRows - 1;
+        constexpr bool kOuterRows = ROLE == 2 || sizeof(T) == 4;   // waves that may hold rows 0 and R-1
+        const unsigned col_xe = (unsigned)(cj * (int)geo.sy + map_index(x_lo ? gi - 1 : gi + 1, geo.nx, geo.closed_x));
+        const unsigned col_ye = (unsigned)(map_index(y_lo ? gj - 1 : gj + 1, geo.ny, geo.closed_y) * (int)geo.sy + ci);
+        const bool xwall_l = wall_face(gi - 1, geo.nx, geo.closed_x);   // the face left of the cell
+        const bool ywall_d = wall_face(gj - 1, geo.ny, geo.closed_y);   // the face below the cell
+        // cells beyond a closed wall (the donor-cell pass gives them the
+        // boundary cell's value): rows by their own row, lanes through the
+        // lane holding the flux of the boundary cell's inner face
+        const bool y_virtual = geo.closed_y && (gj < 0 || gj >= geo.ny);
+        const int gi0 = tx * kTileX - kHX;   // lane 0's column
+        const bool x_edge_tile = DONOR && geo.closed_x && (gi0 < 0 || gi0 + kLanes - 1 >= geo.nx);
+
         auto load = [&](int k, Raw<T>& B) __attribute__((always_inline)) {
             const int ck = map_index(k, geo.nz, geo.closed_z);
-            const long long q = (long long)ck * geo.sz + col;
+            const long long pl = (long long)ck * geo.sz;
+            const long long q = pl + col;
             const long long qv = Tile<T>::tiled_velocities && a.vel_tiled ? (long long)ck * tplane + tcol : q;
-            B.phi = a.phi[q];
-            if (LIMIT) B.psin = a.psin[q];
+            if (!DONOR) B.phi = a.phi[q];
+            if (LIMIT && !DONOR) B.psin = a.psin[q];
             B.u = a.u[qv];
             B.v = a.v[qv];
             B.w = *(has_w ? a.w + qv : a.g + q);
             B.g = a.g[q];
+            if (DONOR) {
+                // psi^n one plane ahead (the donor-cell pass of plane k needs k+1)
+                B.psin = a.psin[(long long)map_index(k + 1, geo.nz, geo.closed_z) * geo.sz + col];
+                if (kXEdgeLoads) {
+                    if (x_lo || x_hi) B.xe = a.psin[pl + col_xe];
+                    if (x_lo) B.cxl = a.u[pl + col_xe];
+                }
+                if (kOuterRows) {
+                    if (y_lo || y_hi) B.yx = a.psin[pl + col_ye];
+                    if (y_lo) B.cyd = a.v[pl + col_ye];
+                }
+            }
         };
 
         // Stages this wave runs (see the row roles below).
@@ -357,6 +429,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
         T bup_p = 0, bdn_p = 0;     // beta at plane k-1
         T fx_p = 0, fy_p = 0;       // x and y fluxes at plane k-1
         T fz_pp = 0;                // z flux at face k-3/2
+        T fz_d = 0;                 // DONOR: the donor-cell z flux at the face below the plane arriving next
         const int t_last = ke + 1;
 
         // Results of march step t (plane t-2 and the velocities of plane
@@ -392,13 +465,84 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             // issued one step ago, have landed: every later wait is free
             vmem_wait_all();
             flush(t - 1);
+            // ---------------- DONOR: psi^(1) of plane t by the donor-cell pass ----------------
+            T phi_t, psin_n;
+            if constexpr (DONOR) {
+                // plane t is the grid plane ck; virtual planes beyond a closed
+                // top repeat plane nz-1, whose psi^(1) the previous step formed
+                const int ck = map_index(t, geo.nz, geo.closed_z);
+                const bool repeat_top = geo.closed_z && t >= geo.nz;
+                const int sd = t & 1;
+                const T p = S.psd[sd][row][lane];       // psi^n of plane ck, published one step ago
+                S.psd[sd ^ 1][row][lane] = R.psin;       // psi^n of plane t+1, for the next step
+                T fxr = zero, fyr = zero, fzr = zero;
+                if (!repeat_top) {
+                    const T U = xwall ? zero : R.u;
+                    const T V = ywall ? zero : R.v;
+                    const T W = (!has_w || wall_face(ck, geo.nz, geo.closed_z)) ? zero : R.w;
+                    const T p_xn = lane_next(p);
+                    const T p_xr = (kXEdgeLoads && x_hi) ? R.xe : p_xn;
+                    const T p_yr = (kOuterRows && y_hi) ? R.yx : S.psd[sd][up][lane];
+                    // below a closed bottom the plane repeats plane 0, whose upper
+                    // neighbour is plane 1 (not the next virtual plane)
+                    T p_zr = R.psin;
+                    if (kMode != kFull && geo.closed_z && t < 0)
+                        p_zr = a.psin[(long long)map_index(1, geo.nz, geo.closed_z) * geo.sz + col];
+                    fxr = pos_f(U) * p + neg_f(U) * p_xr;
+                    fyr = pos_f(V) * p + neg_f(V) * p_yr;
+                    fzr = pos_f(W) * p + neg_f(W) * p_zr;
+                    S.fyd[row][lane] = fyr;
+                }
+                lds_barrier();
+                if (!repeat_top) {
+                    const T cxl = xwall_l ? zero : R.cxl;
+                    const T cyd = ywall_d ? zero : R.cyd;
+                    const T fxl_n = lane_prev(fxr);
+                    T fxl = (kXEdgeLoads && x_lo) ? pos_f(cxl) * R.xe + neg_f(cxl) * p : fxl_n;
+                    T fyl = (kOuterRows && y_lo) ? pos_f(cyd) * R.yx + neg_f(cyd) * p : S.fyd[dn][lane];
+                    const T fzl = (geo.closed_z && ck == 0) ? zero : fz_d;
+                    // A cell beyond a closed wall carries, by the halo rule,
+                    // psi^(1) of the boundary cell it is clamped to: its loads
+                    // are that cell's, and it takes that cell's pair of face
+                    // fluxes (the wall face's is 0) in place of its own.
+                    T fxr_c = fxr, fyr_c = fyr;
+                    if (y_virtual) {
+                        if (gj < 0) {
+                            fyr_c = S.fyd[row - gj][lane];
+                            fyl = zero;
+                        } else {
+                            fyr_c = zero;
+                            fyl = geo.ny >= 2 ? S.fyd[row - (gj - (geo.ny - 2))][lane] : zero;
+                        }
+                    }
+                    if (x_edge_tile) {   // uniform over the workgroup: the tile touches a closed x wall
+                        const int wl = (int)(threadIdx.x & 63);
+                        const int src = gi < 0 ? wl - gi : (gi >= geo.nx ? wl - (gi - (geo.nx >= 2 ? geo.nx - 2 : 0)) : wl);
+                        const T f_src = __shfl(fxr, src, 64);
+                        if (gi < 0) {
+                            fxr_c = f_src;
+                            fxl = zero;
+                        } else if (gi >= geo.nx) {
+                            fxr_c = zero;
+                            fxl = geo.nx >= 2 ? f_src : zero;
+                        }
+                    }
+                    phi_t = p - div_nr(((fxr_c - fxl) + (fyr_c - fyl)) + (fzr - fzl), R.g);
+                    fz_d = fzr;
+                } else {
+                    phi_t = C.phi;
+                }
+                psin_n = p;
+            } else {
+                phi_t = R.phi;
+                psin_n = R.psin;
+            }
             // ---------------- phase 0: plane t arrives ----------------
-            N.phi = R.phi;
+            N.phi = phi_t;
             N.u = xwall ? zero : R.u;
             N.v = ywall ? zero : R.v;
             N.w = (!has_w || wall_face(t, geo.nz, geo.closed_z)) ? zero : R.w;
             N.g = R.g;
-            const T psin_n = R.psin;
             load(t + 1 <= t_last ? t + 1 : t_last, R);   // prefetch the next plane (unconditionally)
             const int sn = t & 1, sc = sn ^ 1;      // ring slots of planes t (= k+1) and k
             N.px = lane_next(N.phi) + N.phi;
@@ -567,6 +711,22 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                                          // phase-2 and phase-3 barriers already separate them
         };
 
+        if constexpr (DONOR) {
+            // psi^n of the first plane into its slot, and the donor-cell z
+            // flux through the face below it (0 at a closed bottom)
+            const int t0 = kb - 2;
+            const int c0 = map_index(t0, geo.nz, geo.closed_z);
+            const T p0 = a.psin[(long long)c0 * geo.sz + col];
+            S.psd[t0 & 1][row][lane] = p0;
+            fz_d = zero;
+            if (!(geo.closed_z && c0 == 0)) {
+                const int cm = map_index(c0 - 1, geo.nz, geo.closed_z);
+                const T pm = a.psin[(long long)cm * geo.sz + col];
+                const T wm = has_w ? a.w[(long long)cm * geo.sz + col] : zero;
+                fz_d = pos_f(wm) * pm + neg_f(wm) * p0;
+            }
+            lds_barrier();
+        }
         load(kb - 2, R);
         step(kb - 2, B0, B1, B2, std::integral_constant<int, kPrimeLoad>{});
         B0 = B1;
@@ -588,25 +748,29 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
 // several rows takes the role of the row that needs most).  FP32 runs every
 // wave in role 0: there only two waves of twelve hold no output row, and
 // the kernel with three loop bodies spills more of its 80 registers.
-template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
-__device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, Slots<T>& S, const int tile,
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false, bool DONOR = false, class SL>
+__device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, SL& S, const int tile,
                                              const int kb, const int ke)
 {
     constexpr int kRows = Tile<T>::rows, kRowsPerWave = 64 / Tile<T>::lanes;
     static_assert(kHalo == 2, "the row roles assume a halo of 2");
     if (sizeof(T) == 4) {
-        pass_rows<T, LIMIT, WRITE_VEL, 0, REC>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 0, REC, DONOR>(geo, a, S, tile, kb, ke);
         return;
     }
     const int r_lo = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) * kRowsPerWave);
     const int r_hi = r_lo + kRowsPerWave - 1;
     if (r_lo <= kRows - 3 && r_hi >= 2)
-        pass_rows<T, LIMIT, WRITE_VEL, 0, REC>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 0, REC, DONOR>(geo, a, S, tile, kb, ke);
     else if (r_lo <= kRows - 2 && r_hi >= 1)
-        pass_rows<T, LIMIT, WRITE_VEL, 1, REC>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 1, REC, DONOR>(geo, a, S, tile, kb, ke);
     else
-        pass_rows<T, LIMIT, WRITE_VEL, 2, REC>(geo, a, S, tile, kb, ke);
+        pass_rows<T, LIMIT, WRITE_VEL, 2, REC, DONOR>(geo, a, S, tile, kb, ke);
 }
+
+// Slots of a pass kernel (the donor-fused pass needs three more planes).
+template <class T, bool DONOR>
+using PassSlots = typename std::conditional<DONOR, SlotsDonor<T>, Slots<T>>::type;
 
 // Logical workgroup id: the dispatcher deals workgroups round-robin over the
 // 8 XCDs; consecutive logical ids (hence neighbouring work) share one XCD.
@@ -620,10 +784,11 @@ __device__ __forceinline__ int xcd_grouped_id()
 // pairs in tile-major order are cut into equal contiguous ranges, one per
 // workgroup, so every workgroup marches the same number of planes (a range
 // may span a tile boundary).
-template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
-__global__ void __launch_bounds__(kThreads, Tile<T>::waves_per_simd) k_pass(Geo geo, PassArgs<T> a)
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false, bool DONOR = false>
+__global__ void __launch_bounds__(kThreads, DONOR ? Tile<T>::donor_waves_per_simd : Tile<T>::waves_per_simd)
+    k_pass(Geo geo, PassArgs<T> a)
 {
-    __shared__ Slots<T> S;
+    __shared__ PassSlots<T, DONOR> S;
     const int nwg = gridDim.x;
     const int wg = xcd_grouped_id();
     const long long total = (long long)a.tiles_x * a.tiles_y * geo.nz;
@@ -635,7 +800,7 @@ __global__ void __launch_bounds__(kThreads, Tile<T>::waves_per_simd) k_pass(Geo 
         const int kb = (int)(w0 - (long long)tile * geo.nz);
         const int ke = (int)((long long)kb + (w1 - w0) < geo.nz ? kb + (w1 - w0) : geo.nz);
         w0 += ke - kb;
-        pass_segment<T, LIMIT, WRITE_VEL, REC>(geo, a, S, tile, kb, ke);
+        pass_segment<T, LIMIT, WRITE_VEL, REC, DONOR>(geo, a, S, tile, kb, ke);
     }
 }
 

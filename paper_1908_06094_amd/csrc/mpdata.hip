@@ -366,15 +366,42 @@ int pass_grid(long long total_planes)
     return n < 8 ? 8 : (int)n;
 }
 
-template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false>
+template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false, bool DONOR = false>
 int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hipStream_t st)
 {
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
     Timed tm(MPDATA_KERNEL_PASS, st);
-    const int grid = pass_grid(total) * mpdata::fused::Tile<T>::wgs_per_cu;
-    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
-    return launch_status("fused corrective pass");
+    using TL = mpdata::fused::Tile<T>;
+    const int grid = pass_grid(total) * (DONOR ? TL::donor_wgs_per_cu : TL::wgs_per_cu);
+    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC, DONOR><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
+    return launch_status(DONOR ? "fused donor-cell and first corrective pass" : "fused corrective pass");
+}
+
+// The first corrective pass with the donor-cell pass folded in (DONOR), or
+// a plain corrective pass.
+template <class T>
+int launch_corrective(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, bool last, bool donor,
+                      hipStream_t st)
+{
+    if (donor) {
+        if (p->limiter)
+            return last ? launch_pass<T, true, false, false, true>(p, a, st)
+                        : launch_pass<T, true, true, false, true>(p, a, st);
+        return last ? launch_pass<T, false, false, false, true>(p, a, st)
+                    : launch_pass<T, false, true, false, true>(p, a, st);
+    }
+    if (p->limiter) return last ? launch_pass<T, true, false>(p, a, st) : launch_pass<T, true, true>(p, a, st);
+    return last ? launch_pass<T, false, false>(p, a, st) : launch_pass<T, false, true>(p, a, st);
+}
+
+// MPDATA_KERNELS=split: the donor-cell pass as its own kernel ahead of the
+// corrective passes (the layout before the donor-cell pass was folded into
+// the first corrective pass; kept as a second fused path for comparison).
+bool use_split_donor()
+{
+    const char* e = getenv("MPDATA_KERNELS");
+    return e && strcmp(e, "split") == 0;
 }
 
 template <class T>
@@ -384,14 +411,16 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     mpdata::Geo g = geo_of(p);
     StepBufs<T> b = carve<T>(p, ws);
     dim3 blk(64, 4, 1);
-    dim3 grd((p->nx + 63) / 64, (p->ny + 3) / 4, p->nz);
+    // the donor-cell pass runs inside the first corrective pass, unless it is
+    // the only pass (or the split layout is asked for)
+    const bool fold = p->iters >= 2 && !use_split_donor();
     T* first_out = p->iters == 1 ? psout : b.phi[0];
-    {
+    if (!fold) {
         Timed tm(MPDATA_KERNEL_DONOR, st);
         dim3 dgrd((p->nx + 63) / 64, (p->ny + 3) / 4, (p->nz + mpdata::fused::kDonorChunk - 1) / mpdata::fused::kDonorChunk);
         mpdata::fused::k_donor_march<T><<<dgrd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, first_out);
+        if (int rc = launch_status("donor-cell pass")) return rc;
     }
-    if (int rc = launch_status("donor-cell pass")) return rc;
 
     mpdata::fused::PassArgs<T> a{};
     a.psin = psin;
@@ -408,17 +437,15 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
     for (int m = 2; m <= p->iters; ++m) {
         const bool last = m == p->iters;
         T* nxt = last ? psout : (phi == b.phi[0] ? b.phi[1] : b.phi[0]);
-        a.phi = phi;
+        const bool donor = fold && m == 2;
+        a.phi = donor ? nullptr : phi;   // the donor-fused pass forms psi^(1) itself
+        a.tiles_x = (p->nx + (donor ? mpdata::fused::Tile<T>::donor_tile_x : mpdata::fused::Tile<T>::tile_x) - 1) /
+                    (donor ? mpdata::fused::Tile<T>::donor_tile_x : mpdata::fused::Tile<T>::tile_x);
         a.out = nxt;
         a.ul = b.vel[vsel][0];
         a.vl = b.vel[vsel][1];
         a.wl = b.vel[vsel][2];
-        int rc;
-        if (p->limiter)
-            rc = last ? launch_pass<T, true, false>(p, a, st) : launch_pass<T, true, true>(p, a, st);
-        else
-            rc = last ? launch_pass<T, false, false>(p, a, st) : launch_pass<T, false, true>(p, a, st);
-        if (rc) return rc;
+        if (int rc = launch_corrective<T>(p, a, last, donor, st)) return rc;
         a.u = a.ul;
         a.v = a.vl;
         a.w = a.wl;

@@ -73,14 +73,16 @@ CASES = [
 ]
 
 
-@pytest.fixture(params=["fused", "stages"])
+@pytest.fixture(params=["fused", "split", "stages"])
 def kernels(request, monkeypatch):
-    """Both kernel paths: the fused k-marching passes (default) and the
-    per-stage kernels (MPDATA_KERNELS=stages)."""
-    if request.param == "stages":
-        monkeypatch.setenv("MPDATA_KERNELS", "stages")
-    else:
+    """Every kernel path: the fused k-marching passes with the donor-cell
+    pass folded into the first of them (default), the same passes behind a
+    separate donor-cell kernel (MPDATA_KERNELS=split), and the per-stage
+    kernels (MPDATA_KERNELS=stages)."""
+    if request.param == "fused":
         monkeypatch.delenv("MPDATA_KERNELS", raising=False)
+    else:
+        monkeypatch.setenv("MPDATA_KERNELS", request.param)
     return request.param
 
 
