@@ -60,15 +60,15 @@ def bytes_per_cell_step(elem, with_cz=True):
     return elem * ((5 if with_cz else 4) + 1)
 
 
-def traffic_record(kernel_src_sha, dtype, workload):
-    """Counter-derived HBM bytes per launch of the fused pass, if the committed
-    record was taken on this workload and on the kernel source as it is now
-    (else None)."""
+def traffic_record(kernel_src_sha, dtype, workload, kernel):
+    """Counter-derived HBM bytes per launch of `kernel`, if the committed
+    record was taken on this workload, on this kernel and on the kernel
+    source as it is now (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_fused_pass_{dtype}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != kernel_src_sha:
+    if rec.get("source_sha256") != kernel_src_sha or rec.get("kernel_kind") != kernel:
         return None
     grid = rec.get("workload", "").split(" ")[0]     # e.g. latlon-1024x512x80
     if not grid or not workload.startswith(grid):
@@ -76,43 +76,69 @@ def traffic_record(kernel_src_sha, dtype, workload):
     return rec.get("bytes_per_launch")
 
 
-def roofline(w, elem, dtype, pass_ms, pass_n, stage_ms, stage_n, ev_ms, steps):
-    """Roofline of the dominant kernel, the fused corrective pass (or, on the
-    per-stage path, all stage kernels of a step taken together, or one whole
-    step under a graph replay): the algorithmic bytes of one cell-step times
-    the cells one launch processes, over the mean launch time.  Returns that
-    record, the same launch time against this library's per-pass word model,
-    and the ALU figure."""
+# Kernel kinds the library times, with the words per cell one launch moves
+# by this library's own accounting (the pass's reads and writes).
+KERNEL_KINDS = {
+    "pass_donor": "first corrective pass with the donor-cell pass folded in (k_pass, DONOR)",
+    "pass": "fused corrective pass (k_pass)",
+    "donor": "donor-cell pass (k_donor_march)",
+    "stage": "per-stage kernels of one step",
+}
+
+
+def model_words(kind, w, last):
+    from paper_1908_06094_amd import model
+
+    if kind == "pass_donor":
+        return 5 + (1 if last else 4)          # psi^n, Cx, Cy, Cz, G; new iterate (+ 3 velocities)
+    if kind == "pass":
+        return model.pass_kernel_words(not last, True)
+    if kind == "donor":
+        return model.donor_kernel_words(True)
+    return model.STEP_WORDS
+
+
+def roofline(w, elem, dtype, fw, steps):
+    """Roofline of the dominant kernel (the timed kernel kind with the largest
+    total time; one whole step under a graph replay): the algorithmic bytes
+    of one cell-step (6 words) times the cells one launch processes, over the
+    mean launch time.  Returns that record, the same launch time against this
+    library's per-launch word model, and the ALU figure."""
     from paper_1908_06094_amd import model, profsum
 
     step_bytes = bytes_per_cell_step(elem) * w.cells
-    if pass_n:
-        avg_s = pass_ms * 1e-3 / pass_n
-        ops = model.corrective_pass_ops(w.limiter)
-        kernel = "fused corrective pass (k_pass)"
-        traffic = traffic_record(profsum.kernel_source_sha(), dtype, w.name)
-        # passes 2..iters-1 also write their limited velocities
-        words = [model.pass_kernel_words(m < w.iters, True) for m in range(2, w.iters + 1)]
-        model_bytes = sum(words) / len(words) * elem * w.cells
+    timed = {k: fw[k] for k in KERNEL_KINDS if fw[k][1]}
+    breakdown = {k: {"launches": n, "avg_launch_us": round(ms * 1e3 / n, 2), "ms_per_step": round(ms / steps, 4)}
+                 for k, (ms, n) in timed.items()}
+    if timed:
+        dom = max(timed, key=lambda k: timed[k][0])
+        ms, n = timed[dom]
+        avg_s = ms * 1e-3 / n
+        kernel = KERNEL_KINDS[dom]
+        traffic = traffic_record(profsum.kernel_source_sha(), dtype, w.name, dom) if dom.startswith("pass") else None
+        # which pass of the step the kind is: the donor-fused pass is pass 2, the plain ones 3 .. iters
+        last = (dom == "pass_donor" and w.iters == 2) or (dom == "pass" and w.iters == 3)
+        model_bytes = model_words(dom, w, last) * elem * w.cells
+        ops = model.corrective_pass_ops(w.limiter) if dom.startswith("pass") else model.step_ops(w.iters, w.limiter)
     else:
-        avg_s = stage_ms * 1e-3 / max(stage_n, 1) if stage_n else ev_ms * 1e-3 / steps
-        ops = model.step_ops(w.iters, w.limiter)
-        kernel = "per-stage kernels of one step" if stage_n else "one whole step (HIP events around the replay)"
+        avg_s = fw["ev_ms"] * 1e-3 / steps
+        kernel = "one whole step (HIP events around the replay)"
         traffic = None
         model_bytes = step_bytes
+        ops = model.step_ops(w.iters, w.limiter)
     achieved = step_bytes / avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_source": (f"committed counter record profiles/traffic_fused_pass_{dtype}.json "
-                               "(FETCH_SIZE x copy factor + WRITE_SIZE per launch; its kernel-source hash matches)"
-                               if traffic is not None else None),
+                               "(FETCH_SIZE x copy factor + WRITE_SIZE per launch; its kernel and kernel-source "
+                               "hash match)" if traffic is not None else None),
             "kernel": kernel, "bytes_per_launch": int(step_bytes),
             "bytes_rule": f"{bytes_per_cell_step(elem)} B per cell (read psi, Cx, Cy, Cz, G; write psi) x {w.cells} cells",
             "avg_launch_us": round(avg_s * 1e6, 2),
-            "step_frac": round(step_bytes * steps / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "step_frac": round(step_bytes * steps / (fw["ev_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels": breakdown}
     pass_model = {"bytes_per_launch": int(model_bytes),
-                  "rule": "the pass's own reads and writes: iterate, psi^n, 3 velocities, G; new iterate "
-                          "(+ 3 limited velocities when another pass follows)",
+                  "rule": "the dominant kernel's own reads and writes per cell",
                   "achieved_GBps": round(model_bytes / avg_s / 1e9, 1),
                   "frac": round(model_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
     ops_s = ops.total * w.cells / avg_s
@@ -165,12 +191,12 @@ def time_forward(mp, torch, dev, w, dtype, steps, warmup, use_graph=False):
     wall = time.perf_counter() - t0
     mp.timing_enable(False)
     r = {"wall": wall, "ev_ms": ev0.elapsed_time(ev1), "graph": graph is not None}
-    r["pass_ms"], r["pass_n"] = mp.timing_read(mp.MPDATA_KERNEL_PASS)
-    r["donor_ms"], r["donor_n"] = mp.timing_read(mp.MPDATA_KERNEL_DONOR)
-    r["stage_ms"], r["stage_n"] = mp.timing_read(mp.MPDATA_KERNEL_STAGE)
-    log(f"[bench] {dtype}: {steps} steps: wall {wall*1e3:.2f} ms, events {r['ev_ms']:.2f} ms; "
-        f"pass kernel {r['pass_n']} x {r['pass_ms'] / max(r['pass_n'], 1):.3f} ms, donor {r['donor_n']} x "
-        f"{r['donor_ms'] / max(r['donor_n'], 1):.3f} ms")
+    r["pass_donor"] = mp.timing_read(mp.MPDATA_KERNEL_PASS_DONOR)
+    r["pass"] = mp.timing_read(mp.MPDATA_KERNEL_PASS)
+    r["donor"] = mp.timing_read(mp.MPDATA_KERNEL_DONOR)
+    r["stage"] = mp.timing_read(mp.MPDATA_KERNEL_STAGE)
+    log(f"[bench] {dtype}: {steps} steps: wall {wall*1e3:.2f} ms, events {r['ev_ms']:.2f} ms; " +
+        ", ".join(f"{k} {r[k][1]} x {r[k][0] / r[k][1]:.3f} ms" for k in KERNEL_KINDS if r[k][1]))
     del psi, cx, cy, cz, g, ws
     return r
 
@@ -369,24 +395,19 @@ def main():
     dev = torch.device("cuda:0")
     fw = time_forward(mp, torch, dev, w, args.dtype, args.steps, args.warmup, args.graph)
     wall, ev_ms = fw["wall"], fw["ev_ms"]
-    pass_ms, pass_n, donor_ms, donor_n = fw["pass_ms"], fw["pass_n"], fw["donor_ms"], fw["donor_n"]
     ms_per_step = wall * 1e3 / args.steps
     updates = w.cells * args.steps / wall
-    roof, pass_model, alu = roofline(w, elem, args.dtype, pass_ms, pass_n, fw["stage_ms"], fw["stage_n"], ev_ms,
-                                     args.steps)
+    roof, pass_model, alu = roofline(w, elem, args.dtype, fw, args.steps)
 
     # the FP32 leg of the same workload (inputs already FP32-representable)
     fp32 = None
     if args.dtype == "f64" and not args.no_fp32:
         f3 = time_forward(mp, torch, dev, w, "f32", args.steps, args.warmup, args.graph)
-        r32, m32, _ = roofline(w, 4, "f32", f3["pass_ms"], f3["pass_n"], f3["stage_ms"], f3["stage_n"], f3["ev_ms"],
-                               args.steps)
+        r32, m32, _ = roofline(w, 4, "f32", f3, args.steps)
         fp32 = {"value": round(w.cells * args.steps / f3["wall"], 1), "unit": "grid-point updates/s",
                 "ms_per_step": round(f3["wall"] * 1e3 / args.steps, 4),
                 "ms_per_step_events": round(f3["ev_ms"] / args.steps, 4),
                 "roofline": r32, "roofline_pass_model": m32,
-                "pass_launches": f3["pass_n"], "pass_ms_avg": round(f3["pass_ms"] / max(f3["pass_n"], 1), 4),
-                "donor_launches": f3["donor_n"], "donor_ms_avg": round(f3["donor_ms"] / max(f3["donor_n"], 1), 4),
                 "speedup_vs_f64": round(wall / f3["wall"], 3)}
 
     adjoint = None
@@ -493,9 +514,7 @@ def main():
         "roofline_alu": alu,
         "fp32": fp32,
         "step": {"ms_per_step_events": round(ev_ms / args.steps, 4),
-                 "hbm_frac_step": roof["step_frac"],
-                 "pass_launches": pass_n, "pass_ms_avg": round(pass_ms / max(pass_n, 1), 4),
-                 "donor_launches": donor_n, "donor_ms_avg": round(donor_ms / max(donor_n, 1), 4)},
+                 "hbm_frac_step": roof["step_frac"]},
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "hbm_copy": {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),

@@ -240,11 +240,15 @@ const char* mpdata_last_error(void);
  * the record.
  * mpdata_timing_read() waits for the recorded events of one kernel kind and
  * returns the summed elapsed milliseconds and the number of launches.  Kinds:
- *   MPDATA_KERNEL_PASS   the fused corrective-pass kernel
- *   MPDATA_KERNEL_DONOR  the donor-cell pass ahead of the fused passes
- *   MPDATA_KERNEL_STAGE  the per-stage kernels (MPDATA_KERNELS=stages)
- *   MPDATA_KERNEL_USTEP  the unstructured step kernel */
-enum { MPDATA_KERNEL_PASS = 0, MPDATA_KERNEL_DONOR = 1, MPDATA_KERNEL_STAGE = 2, MPDATA_KERNEL_USTEP = 3 };
+ *   MPDATA_KERNEL_PASS        the fused corrective-pass kernel (passes 3 ..)
+ *   MPDATA_KERNEL_DONOR       a separate donor-cell pass (one-pass steps,
+ *                             MPDATA_KERNELS=split, batched runs)
+ *   MPDATA_KERNEL_STAGE       the per-stage kernels (MPDATA_KERNELS=stages)
+ *   MPDATA_KERNEL_USTEP       the unstructured step kernel
+ *   MPDATA_KERNEL_PASS_DONOR  the first corrective pass with the donor-cell
+ *                             pass folded in */
+enum { MPDATA_KERNEL_PASS = 0, MPDATA_KERNEL_DONOR = 1, MPDATA_KERNEL_STAGE = 2, MPDATA_KERNEL_USTEP = 3,
+       MPDATA_KERNEL_PASS_DONOR = 4 };
 int mpdata_timing_enable(int32_t on);
 int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches);
 

@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     MPDATA_F64,
     MPDATA_KERNEL_DONOR,
     MPDATA_KERNEL_PASS,
+    MPDATA_KERNEL_PASS_DONOR,
     MPDATA_KERNEL_STAGE,
     MPDATA_KERNEL_USTEP,
     MPDATA_OP_ADJOINT,

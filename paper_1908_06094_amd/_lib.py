@@ -61,7 +61,7 @@ _SIGNATURES = {
                            ctypes.c_int),
 }
 
-MPDATA_KERNEL_PASS, MPDATA_KERNEL_DONOR, MPDATA_KERNEL_STAGE, MPDATA_KERNEL_USTEP = 0, 1, 2, 3
+MPDATA_KERNEL_PASS, MPDATA_KERNEL_DONOR, MPDATA_KERNEL_STAGE, MPDATA_KERNEL_USTEP, MPDATA_KERNEL_PASS_DONOR = 0, 1, 2, 3, 4
 
 
 def lib_path() -> str:

@@ -213,7 +213,7 @@ int debug_check(int dtype, long long n, int count, const void* psi, const void* 
 struct KernelTiming {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[4];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[5];
     std::vector<hipEvent_t> spare;
 };
 KernelTiming g_timing;
@@ -371,7 +371,7 @@ int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hi
 {
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
-    Timed tm(MPDATA_KERNEL_PASS, st);
+    Timed tm(DONOR ? MPDATA_KERNEL_PASS_DONOR : MPDATA_KERNEL_PASS, st);
     using TL = mpdata::fused::Tile<T>;
     const int grid = pass_grid(total) * (DONOR ? TL::donor_wgs_per_cu : TL::wgs_per_cu);
     mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC, DONOR><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
@@ -1233,7 +1233,7 @@ int mpdata_timing_enable(int32_t on)
 
 int mpdata_timing_read(int32_t kind, double* total_ms, int64_t* launches)
 {
-    if (kind < 0 || kind > 3) return fail(MPDATA_EINVAL, "timing kind %d is not an MPDATA_KERNEL_* value", kind);
+    if (kind < 0 || kind > 4) return fail(MPDATA_EINVAL, "timing kind %d is not an MPDATA_KERNEL_* value", kind);
     if (!total_ms || !launches) return fail(MPDATA_EINVAL, "output pointers must not be NULL");
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double sum = 0.0;

@@ -4,7 +4,7 @@ counter means, and counter-derived HBM traffic of one kernel.
     python -m paper_1908_06094_amd.profsum trace DIR
     python -m paper_1908_06094_amd.profsum counters DIR
     python -m paper_1908_06094_amd.profsum traffic --fetch DIR --write DIR --kernel SUBSTR \
-        --copy-bytes N [--out JSON --workload TEXT --command CMD ...]
+        --copy-bytes N [--kind KIND --out JSON --workload TEXT --command CMD ...]
 
 ``traffic`` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the
 kernels whose name contains SUBSTR by the ratio each counter shows for a plain
@@ -117,6 +117,7 @@ def _main(argv):
     r.add_argument("--fetch", required=True)
     r.add_argument("--write", required=True)
     r.add_argument("--kernel", required=True)
+    r.add_argument("--kind", default="pass", help="the timing kind bench.py reports the kernel under")
     r.add_argument("--copy-bytes", type=int, required=True)
     r.add_argument("--workload", default="")
     r.add_argument("--command", action="append", default=[])
@@ -130,7 +131,7 @@ def _main(argv):
         for k, d in sorted(counters(a.path).items()):
             print(k[:70], " ".join(f"{n}={v:.0f}" for n, v in sorted(d.items())))
     else:
-        rec = {"kernel": a.kernel, "workload": a.workload, "source_sha256": kernel_source_sha(),
+        rec = {"kernel": a.kernel, "kernel_kind": a.kind, "workload": a.workload, "source_sha256": kernel_source_sha(),
                "commands": a.command}
         rec.update(traffic(a.fetch, a.write, a.kernel, a.copy_bytes))
         text = json.dumps(rec, indent=1)

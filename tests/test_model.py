@@ -52,15 +52,17 @@ def test_traffic_record_matches_kernel_source_and_workload():
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
                         "traffic_fused_pass_f64.json")
     rec = json.load(open(path))
+    kind = rec.get("kernel_kind", "pass")
     sha = profsum.kernel_source_sha()
     if rec["source_sha256"] == sha:
-        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave") == rec["bytes_per_launch"]
+        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave", kind) == rec["bytes_per_launch"]
     else:   # a stale record (the kernel changed since the counters were taken) is never attached
-        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave") is None
+        assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave", kind) is None
     sha = rec["source_sha256"]
-    assert bench.traffic_record(sha, "f64", "latlon-256x128x60-solid-body") is None
-    assert bench.traffic_record("0" * 64, "f64", "latlon-1024x512x80-wave") is None
-    # calibrated counter bytes per launch: fetched x copy factor + written, averaged over the two passes
+    assert bench.traffic_record(sha, "f64", "latlon-256x128x60-solid-body", kind) is None
+    assert bench.traffic_record("0" * 64, "f64", "latlon-1024x512x80-wave", kind) is None
+    assert bench.traffic_record(sha, "f64", "latlon-1024x512x80-wave", "stage") is None   # another kernel
+    # calibrated counter bytes per launch: fetched x copy factor + written, averaged over the matching kernels
     f = rec["copy_calibration"]["fetch_factor"]
     kib = [rec["fetch_kib_per_dispatch"][k] * f + rec["write_kib_per_dispatch"][k] for k in rec["fetch_kib_per_dispatch"]]
     assert abs(sum(kib) / len(kib) * 1024 - rec["bytes_per_launch"]) <= 1e-6 * rec["bytes_per_launch"]
