@@ -160,12 +160,25 @@ int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_e
  * NULL.  Items must not share psi storage.  Flags:
  *   MPDATA_BATCH_GRAPH  capture the nsteps steps into a HIP graph on first
  *                       use and replay it (cached per item pointers, sizes,
- *                       nsteps, workspace and device);
- *   MPDATA_BATCH_TUNE   pick the kernel variant (one or two workgroups per
- *                       CU) by timing one step of each on this batch; the
+ *                       nsteps, workspace, kernel variant and device);
+ *   MPDATA_BATCH_TUNE   pick the kernel variant by timing one step of each
+ *                       on this batch (FP32: tile rows of 32, 64 or 16 lanes,
+ *                       i.e. 28 x 20, 60 x 8 or 12 x 44 interior cells per
+ *                       768-thread tile, times one or two workgroups per CU,
+ *                       times the donor-cell pass inside the first
+ *                       corrective pass or as its own kernel: variants
+ *                       0 .. 5 = (32, 1), (32, 2), (64, 1), (64, 2), (16, 1),
+ *                       (16, 2) folded and 6 .. 11 the same split; FP64:
+ *                       0 folded, 1 split, 64 lanes, one workgroup); the
  *                       choice is kept per batch shape and appended to the
  *                       file named by the environment variable
- *                       MPDATA_TUNE_CACHE.  Tuning synchronises `stream`.
+ *                       MPDATA_TUNE_CACHE as a line "<batch shape>\t<variant>"
+ *                       (a different file name is read afresh).  Tuning
+ *                       synchronises `stream`; a tuning step reads the
+ *                       caller's fields and writes only the workspace.
+ * Without a tuned choice the variant is 0.  The environment variable
+ * MPDATA_BATCH_VARIANT forces a variant (an index outside the dtype's
+ * variants is MPDATA_EINVAL).
  * ws: at least mpdata_batch_workspace_bytes() for the same items.  The
  * paper's fusion and caching of the flux stages (Section 6.1, Table 2,
  * Listing 9) is what the fused pass applies; batching is this library's. */

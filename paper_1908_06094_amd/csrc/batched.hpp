@@ -7,10 +7,14 @@
 // no load imbalance, and the tracers of one tile run on neighbouring
 // workgroups of one XCD (their shared winds and G then come from that L2).
 //
-// The autotuner picks, per batch signature, between the fused pass with one
-// workgroup per CU and (FP32) the variant compiled for two workgroups per CU,
-// by timing one step of each on the caller's data; choices are kept in memory
-// and appended to the file named by MPDATA_TUNE_CACHE.
+// The autotuner picks, per batch signature, the kernel variant: in FP32 the
+// tile row width (16, 32 or 64 lanes: 12 x 44, 28 x 20 or 60 x 8 interior
+// cells per 768-thread tile) and the workgroups per CU (one, or two with at
+// most 80 registers); in both types whether the first corrective pass
+// carries the donor-cell pass (as in the single-problem path) or a separate
+// donor-cell kernel runs ahead of it.  It times one step of each on the
+// caller's data; choices are kept in memory and appended to the file named
+// by MPDATA_TUNE_CACHE.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -119,24 +123,30 @@ struct Tables {
     std::vector<mpdata::fused::DonorBlocks<T>> donor[2];  // by step parity
     std::vector<std::vector<BatchEntry<T>>> pass[2];    // [parity][m - 2]
     std::vector<DonorEntry<T>> copyback;                // S -> user (odd step counts)
-    long long donor_total = 0, pass_total = 0, donor_blocks = 0;
+    long long donor_total = 0, donor_blocks = 0;
+    std::vector<long long> pass_total;                  // work units of pass m, [m - 2]
+    bool fold = false;                                  // the first corrective pass runs the donor-cell pass
 };
 
-template <class T>
-Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* items, const Layout& L, char* ws)
+// Tables for the tile of row width LANES.  fold: the donor-cell pass runs
+// inside the first corrective pass (its tile may be narrower, FP64).
+template <class T, int LANES>
+Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* items, const Layout& L, char* ws,
+                       bool fold)
 {
+    using TL = mpdata::fused::Tile<T, LANES>;
     Tables<T> tb;
     const int M = c->iters;
     const double eps = c->eps > 0.0 ? c->eps : 1e-15;
+    tb.fold = fold && M >= 2;
     for (int par = 0; par < 2; ++par) tb.pass[par].resize(M > 1 ? M - 1 : 0);
-    long long dbeg = 0, pbeg = 0, bbeg = 0;
+    tb.pass_total.assign(M > 1 ? M - 1 : 0, 0);
+    long long dbeg = 0, bbeg = 0;
     for (int i = 0; i < n; ++i) {
         const mpdata_batch_item& it = items[i];
         const ItemPtrs<T> P = item_ptrs<T>(L, ws, it, i);
         const Geo g = geo_of_item(c, it);
         const long long cells = L.cells[i];
-        const int tiles = ((it.nx + mpdata::fused::Tile<T>::tile_x - 1) / mpdata::fused::Tile<T>::tile_x) *
-                          ((it.ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y);
         for (int par = 0; par < 2; ++par) {
             T* src = par == 0 ? P.user : P.f[2];
             T* dst = par == 0 ? P.f[2] : P.user;
@@ -156,10 +166,14 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
             d.tracers = it.ntracers;
             tb.donor[par].push_back(d);
             for (int m = 2; m <= M; ++m) {
+                const bool donor = tb.fold && m == 2;
+                const int tile_x = donor ? TL::donor_tile_x : TL::tile_x;
+                const int tiles_x = (it.nx + tile_x - 1) / tile_x;
+                const int tiles = tiles_x * ((it.ny + TL::tile_y - 1) / TL::tile_y);
                 BatchEntry<T> e{};
                 e.geo = g;
                 PassArgs<T>& a = e.args;
-                a.phi = P.f[(m - 2) & 1];               // X_{m-1}: X0, X1, X0, ...
+                a.phi = donor ? nullptr : P.f[(m - 2) & 1];   // X_{m-1}: X0, X1, X0, ... (the donor-fused pass forms it)
                 a.out = m == M ? dst : P.f[(m - 1) & 1];
                 a.psin = src;
                 if (m == 2) {
@@ -178,15 +192,16 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
                 a.wl = m < M ? vout[2] : nullptr;
                 a.g = (const T*)it.g;
                 a.eps = eps;
-                a.tiles_x = (it.nx + mpdata::fused::Tile<T>::tile_x - 1) / mpdata::fused::Tile<T>::tile_x;
-                a.tiles_y = (it.ny + mpdata::fused::Tile<T>::tile_y - 1) / mpdata::fused::Tile<T>::tile_y;
-                e.begin = pbeg;
+                a.tiles_x = tiles_x;
+                a.tiles_y = (it.ny + TL::tile_y - 1) / TL::tile_y;
+                e.begin = tb.pass_total[m - 2];
                 e.tracer_stride = cells;
                 e.vel_stride = L.vcells[i];
                 e.tracers = it.ntracers;
                 e.vel_per_tracer = m > 2;
-                a.vel_tiled = m > 2 && mpdata::fused::Tile<T>::tiled_velocities;
+                a.vel_tiled = m > 2 && TL::tiled_velocities;
                 tb.pass[par][m - 2].push_back(e);
+                if (par == 1) tb.pass_total[m - 2] += (long long)tiles * it.ntracers * it.nz;
             }
         }
         DonorEntry<T> cb;
@@ -202,11 +217,9 @@ Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* 
         const mpdata::fused::DonorBlocks<T>& d0 = tb.donor[0].back();
         bbeg += (long long)d0.bx * d0.by * d0.bz * it.ntracers;
         dbeg += cells * it.ntracers;
-        pbeg += (long long)tiles * it.ntracers * it.nz;
     }
     tb.donor_total = dbeg;
     tb.donor_blocks = bbeg;
-    tb.pass_total = pbeg;
     return tb;
 }
 

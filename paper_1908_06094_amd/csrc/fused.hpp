@@ -59,11 +59,19 @@ namespace fused {
 constexpr int kThreads = 768;                // 12 waves: 3 per SIMD, up to 168 VGPRs each
 constexpr int kHalo = 2;
 
-// Tile shape per element type: a tile row is `lanes` wide (a wave holds
-// 64 / lanes rows) and the workgroup's 768 threads hold `rows` rows.
+// Default tile row width per element type.
 template <class T>
+struct DefaultLanes {
+    static constexpr int value = sizeof(T) == 8 ? MPDATA_ROW_LANES_F64 : MPDATA_ROW_LANES_F32;
+};
+
+// Tile shape: a tile row is L lanes wide (a wave holds 64 / L rows) and the
+// workgroup's 768 threads hold `rows` rows.  The single-problem passes use
+// the default width of their type; the batched passes are also compiled for
+// the other widths, among which the autotuner picks.
+template <class T, int L = DefaultLanes<T>::value>
 struct Tile {
-    static constexpr int lanes = sizeof(T) == 8 ? MPDATA_ROW_LANES_F64 : MPDATA_ROW_LANES_F32;
+    static constexpr int lanes = L;
     static constexpr int shift = lanes == 64 ? 6 : (lanes == 32 ? 5 : 4);
     static constexpr int rows = kThreads / lanes;
     static constexpr int tile_x = lanes - 2 * kHalo;   // interior columns
@@ -74,8 +82,10 @@ struct Tile {
     static constexpr int waves_per_simd = wgs_per_cu * kThreads / 256;
     // velocities handed between passes in the tile layout (FP32: its 112-byte
     // tile rows make the (nz, ny, nx) stores mostly partial cache lines; in
-    // FP64 the 480-byte rows are not, and the tile layout measured slower)
-    static constexpr bool tiled_velocities = sizeof(T) == 4;
+    // FP64 the 480-byte rows are not, and the tile layout measured slower).
+    // The layout is that of the default FP32 tile; other widths hand their
+    // velocities over as (nz, ny, nx) fields.
+    static constexpr bool tiled_velocities = sizeof(T) == 4 && L == DefaultLanes<T>::value;
     static_assert((1 << shift) == lanes && lanes >= 16 && lanes <= 64, "a tile row is 16, 32 or 64 lanes");
     // The pass with the donor-cell pass folded in (DONOR).  FP64 widens its x
     // halo to 3 (58 interior columns), so that psi^(1) is needed on lanes
@@ -269,9 +279,9 @@ __device__ __forceinline__ int map_index(int x, int n, int closed)
 // Is the face x+1/2 (virtual x) a closed wall or beyond one?
 __device__ __forceinline__ bool wall_face(int x, int n, int closed) { return closed && (x < 0 || x >= n - 1); }
 
-template <class T>
+template <class T, int L = DefaultLanes<T>::value>
 struct Slots {
-    static constexpr int kRows = Tile<T>::rows, kLanes = Tile<T>::lanes;
+    static constexpr int kRows = Tile<T, L>::rows, kLanes = L;
     // y-exchange planes, one value per (row, lane); phi, px and vpx keep the
     // last two planes (slot = plane parity) so that plane k's neighbours are
     // read one march step after they were published
@@ -287,10 +297,10 @@ struct Slots {
 // plane slots: psi^n of the current plane and of the next (ring by plane
 // parity; the y neighbours of the donor-cell fluxes) and the donor-cell y
 // flux at each row's upper face, which the row above reads.
-template <class T>
-struct SlotsDonor : Slots<T> {
-    T psd[2][Tile<T>::rows][Tile<T>::lanes];
-    T fyd[Tile<T>::rows][Tile<T>::lanes];
+template <class T, int L = DefaultLanes<T>::value>
+struct SlotsDonor : Slots<T, L> {
+    T psd[2][Tile<T, L>::rows][L];
+    T fyd[Tile<T, L>::rows][L];
 };
 
 // One column's values of one plane: the loaded fields and what is derived
@@ -333,17 +343,18 @@ template <class T, bool LIMIT, bool WRITE_VEL, int ROLE, bool REC, bool DONOR, c
 __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, SL& S, const int tile,
                                           const int kb, const int ke)
 {
-    constexpr int kLanes = Tile<T>::lanes, kRows = Tile<T>::rows;
-    constexpr int kTileY = Tile<T>::tile_y;
+    using TL = Tile<T, SL::kLanes>;
+    constexpr int kLanes = TL::lanes, kRows = TL::rows;
+    constexpr int kTileY = TL::tile_y;
     // x halo and interior width of this kernel (the donor-fused FP64 pass
     // widens its x halo); the tile layout of handed-over velocities keeps the
     // plain pass's interior
-    constexpr int kHX = DONOR ? Tile<T>::donor_halo_x : kHalo;
+    constexpr int kHX = DONOR ? TL::donor_halo_x : kHalo;
     constexpr int kTileX = kLanes - 2 * kHX;
-    constexpr int kLayX = Tile<T>::tile_x;
+    constexpr int kLayX = TL::tile_x;
     constexpr bool kXEdgeLoads = DONOR && kHX == kHalo;   // row-end lanes load their outer neighbour
     const int lane = threadIdx.x & (kLanes - 1);
-    const int row = threadIdx.x >> Tile<T>::shift;
+    const int row = threadIdx.x >> TL::shift;
     const int up = row < kRows - 1 ? row + 1 : row;     // clamped: the edge rows are halo
     const int dn = row > 0 ? row - 1 : row;
     const T eps = (T)a.eps;
@@ -394,7 +405,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             const int ck = map_index(k, geo.nz, geo.closed_z);
             const long long pl = (long long)ck * geo.sz;
             const long long q = pl + col;
-            const long long qv = Tile<T>::tiled_velocities && a.vel_tiled ? (long long)ck * tplane + tcol : q;
+            const long long qv = TL::tiled_velocities && a.vel_tiled ? (long long)ck * tplane + tcol : q;
             if (!DONOR) B.phi = a.phi[q];
             if (LIMIT && !DONOR) B.psin = a.psin[q];
             B.u = a.u[qv];
@@ -440,8 +451,8 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             const int ko = t - 2;
             const long long q0 = (long long)ko * geo.sz + col;
             const long long v0 = (long long)ko * tplane + tcol;
-            const long long w0 = Tile<T>::tiled_velocities ? v0 : q0;
-            const long long wstep = Tile<T>::tiled_velocities ? tplane : geo.sz;
+            const long long w0 = TL::tiled_velocities ? v0 : q0;
+            const long long wstep = TL::tiled_velocities ? tplane : geo.sz;
             if (writer && ko >= kb && ko < ke) {
                 a.out[q0] = st_upd;
                 if (WRITE_VEL) a.wl[w0] = st_ulz;     // face (k-1)+1/2
@@ -752,7 +763,7 @@ template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false, bool DONOR = fa
 __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& a, SL& S, const int tile,
                                              const int kb, const int ke)
 {
-    constexpr int kRows = Tile<T>::rows, kRowsPerWave = 64 / Tile<T>::lanes;
+    constexpr int kRows = SL::kRows, kRowsPerWave = 64 / SL::kLanes;
     static_assert(kHalo == 2, "the row roles assume a halo of 2");
     if (sizeof(T) == 4) {
         pass_rows<T, LIMIT, WRITE_VEL, 0, REC, DONOR>(geo, a, S, tile, kb, ke);
@@ -769,8 +780,8 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
 }
 
 // Slots of a pass kernel (the donor-fused pass needs three more planes).
-template <class T, bool DONOR>
-using PassSlots = typename std::conditional<DONOR, SlotsDonor<T>, Slots<T>>::type;
+template <class T, bool DONOR, int L = DefaultLanes<T>::value>
+using PassSlots = typename std::conditional<DONOR, SlotsDonor<T, L>, Slots<T, L>>::type;
 
 // Logical workgroup id: the dispatcher deals workgroups round-robin over the
 // 8 XCDs; consecutive logical ids (hence neighbouring work) share one XCD.
@@ -823,11 +834,11 @@ struct BatchEntry {
 
 // WAVES_PER_SIMD: 3 = one workgroup per CU (up to 168 VGPRs per wave);
 // 6 = two workgroups per CU (the FP32 kernel's LDS allows it; VGPRs <= 80).
-template <class T, bool LIMIT, bool WRITE_VEL, int WAVES_PER_SIMD>
+template <class T, bool LIMIT, bool WRITE_VEL, int WAVES_PER_SIMD, bool DONOR = false, int L = DefaultLanes<T>::value>
 __global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const BatchEntry<T>* __restrict__ tab,
                                                                            int n_entries, long long total)
 {
-    __shared__ Slots<T> S;
+    __shared__ PassSlots<T, DONOR, L> S;
     const int nwg = gridDim.x;
     const int wg = xcd_grouped_id();
     const long long span = (total + nwg - 1) / nwg;
@@ -851,7 +862,7 @@ __global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const
         w0 += ke - kb;
         PassArgs<T> a = e.args;
         const long long off = (long long)tracer * e.tracer_stride;
-        a.phi += off;
+        if (!DONOR) a.phi += off;   // the donor-fused pass reads no iterate
         a.psin += off;
         a.out += off;
         const long long voff = (long long)tracer * e.vel_stride;
@@ -865,7 +876,7 @@ __global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const
             a.vl += voff;
             a.wl += voff;
         }
-        pass_segment<T, LIMIT, WRITE_VEL>(e.geo, a, S, tile, kb, ke);
+        pass_segment<T, LIMIT, WRITE_VEL, false, DONOR>(e.geo, a, S, tile, kb, ke);
     }
 }
 

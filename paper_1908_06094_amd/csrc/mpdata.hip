@@ -820,9 +820,27 @@ struct BatchCacheEntry {
 
 std::mutex g_batch_mu;
 std::map<std::string, BatchCacheEntry> g_batch_cache;
-std::map<std::string, int> g_tuned;          // batch shape -> variant
+std::map<std::string, int> g_tuned;          // batch shape -> variant (from tuning or MPDATA_TUNE_CACHE)
+std::string g_tune_path;                     // the cache file g_tuned was read from
 bool g_tune_file_read = false;
 hipStream_t g_capture_stream[64] = {nullptr};
+
+// Kernel variants of the batched passes: the tile row width, the
+// workgroups per CU (waves per SIMD) and whether the donor-cell pass runs
+// inside the first corrective pass or as its own kernel (in FP32 the
+// separate donor-cell kernel is cheap, half the bytes of FP64, and the
+// folded one costs about as much in arithmetic, so which is faster depends
+// on the batch).  FP32 has twelve variants, FP64 two.
+struct BatchVariant {
+    int lanes, waves_per_simd;
+    bool fold;
+};
+constexpr BatchVariant kVariantsF32[] = {{32, 3, true},  {32, 6, true},  {64, 3, true},  {64, 6, true},
+                                         {16, 3, true},  {16, 6, true},  {32, 3, false}, {32, 6, false},
+                                         {64, 3, false}, {64, 6, false}, {16, 3, false}, {16, 6, false}};
+constexpr BatchVariant kVariantsF64[] = {{64, 3, true}, {64, 3, false}};
+int variant_count(int dtype) { return dtype == MPDATA_F32 ? 12 : 2; }
+BatchVariant variant_of(int dtype, int v) { return dtype == MPDATA_F32 ? kVariantsF32[v] : kVariantsF64[v]; }
 
 std::string shape_key(const mpdata_problem* c, int n, const mpdata_batch_item* items)
 {
@@ -838,11 +856,17 @@ std::string shape_key(const mpdata_problem* c, int n, const mpdata_batch_item* i
     return k;
 }
 
+// (Re-)reads the tuning cache named by MPDATA_TUNE_CACHE whenever that name
+// differs from the one read last: the choices of one cache file never
+// answer for another.
 void read_tune_file()
 {
-    if (g_tune_file_read) return;
-    g_tune_file_read = true;
     const char* path = getenv("MPDATA_TUNE_CACHE");
+    const std::string now = path ? path : "";
+    if (g_tune_file_read && now == g_tune_path) return;
+    g_tuned.clear();
+    g_tune_path = now;
+    g_tune_file_read = true;
     if (!path) return;
     FILE* f = fopen(path, "r");
     if (!f) return;
@@ -873,41 +897,81 @@ struct BatchDev {
     const mpdata::stages::DonorEntry<T>* copyback;
 };
 
-template <class T>
-int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv, int par,
-                         int variant, hipStream_t st)
+// One step's launches for the variant of row width LANES and WPS waves per
+// SIMD: the donor-cell pass unless the first corrective pass carries it,
+// then the corrective passes.
+template <class T, int LANES, int WPS>
+int enqueue_batched_step_v(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv, int par,
+                           hipStream_t st)
 {
     const int cus = cu_count();
-    {
+    if (!tb.fold) {
         Timed td(MPDATA_KERNEL_DONOR, st);
         mpdata::fused::k_donor_march_batched<T><<<(unsigned)tb.donor_blocks, 256, 0, st>>>(dv.donor[par], n);
+        if (int rc = launch_status("batched donor-cell pass")) return rc;
     }
-    if (int rc = launch_status("batched donor-cell pass")) return rc;
-    // two workgroups per CU only fit the LDS in single precision
-    constexpr int kOcc2 = sizeof(T) == 4 ? 6 : 3;
-    if (sizeof(T) != 4) variant = 0;
     for (int m = 2; m <= c->iters; ++m) {
         const bool last = m == c->iters;
+        const bool donor = tb.fold && m == 2;
         const mpdata::fused::BatchEntry<T>* tab = dv.pass[par][m - 2];
-        const long long total = tb.pass_total;
+        const long long total = tb.pass_total[m - 2];
         long long g1 = std::min<long long>(cus, std::max<long long>(8, (total / 12) & ~7LL));
         g1 &= ~7LL;
         if (g1 < 8) g1 = 8;
-        const int grid = (int)(variant == 1 ? g1 * 2 : g1);
-        Timed tm(MPDATA_KERNEL_PASS, st);
-#define MPDATA_LAUNCH(LIM, WV, OCC) \
-    mpdata::fused::k_pass_batched<T, LIM, WV, OCC><<<grid, mpdata::fused::kThreads, 0, st>>>(tab, n, total)
-        if (variant == 1) {
-            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, kOcc2); else MPDATA_LAUNCH(true, true, kOcc2); }
-            else { if (last) MPDATA_LAUNCH(false, false, kOcc2); else MPDATA_LAUNCH(false, true, kOcc2); }
+        const int grid = (int)(WPS == 6 ? g1 * 2 : g1);
+        Timed tm(donor ? MPDATA_KERNEL_PASS_DONOR : MPDATA_KERNEL_PASS, st);
+#define MPDATA_LAUNCH(LIM, WV, DN) \
+    mpdata::fused::k_pass_batched<T, LIM, WV, WPS, DN, LANES><<<grid, mpdata::fused::kThreads, 0, st>>>(tab, n, total)
+        if (donor) {
+            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, true); else MPDATA_LAUNCH(true, true, true); }
+            else { if (last) MPDATA_LAUNCH(false, false, true); else MPDATA_LAUNCH(false, true, true); }
         } else {
-            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, 3); else MPDATA_LAUNCH(true, true, 3); }
-            else { if (last) MPDATA_LAUNCH(false, false, 3); else MPDATA_LAUNCH(false, true, 3); }
+            if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, false); else MPDATA_LAUNCH(true, true, false); }
+            else { if (last) MPDATA_LAUNCH(false, false, false); else MPDATA_LAUNCH(false, true, false); }
         }
 #undef MPDATA_LAUNCH
         if (int rc = launch_status("batched corrective pass")) return rc;
     }
     return MPDATA_OK;
+}
+
+template <class T>
+int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv, int par,
+                         int variant, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 8) {
+        return variant >= 0 && variant < 2 ? enqueue_batched_step_v<T, 64, 3>(c, n, tb, dv, par, st)
+                                           : fail(MPDATA_EINVAL, "batched kernel variant %d does not exist in FP64",
+                                                  variant);
+    } else {
+        // the fold is the tables' (variants v and v + 6 share their kernels)
+        switch (variant % 6) {
+        case 0: return enqueue_batched_step_v<T, 32, 3>(c, n, tb, dv, par, st);
+        case 1: return enqueue_batched_step_v<T, 32, 6>(c, n, tb, dv, par, st);
+        case 2: return enqueue_batched_step_v<T, 64, 3>(c, n, tb, dv, par, st);
+        case 3: return enqueue_batched_step_v<T, 64, 6>(c, n, tb, dv, par, st);
+        case 4: return enqueue_batched_step_v<T, 16, 3>(c, n, tb, dv, par, st);
+        case 5: return enqueue_batched_step_v<T, 16, 6>(c, n, tb, dv, par, st);
+        default: return fail(MPDATA_EINVAL, "batched kernel variant %d does not exist", variant);
+        }
+    }
+}
+
+// Tables for a variant (its tile width decides the work units).
+template <class T>
+batch::Tables<T> tables_for(const mpdata_problem* c, int n, const mpdata_batch_item* items, const batch::Layout& L,
+                            char* ws, int variant)
+{
+    // MPDATA_KERNELS=split keeps the donor-cell pass separate whatever the variant
+    const bool fold = c->iters >= 2 && !use_split_donor() && variant_of(c->dtype, variant).fold;
+    if constexpr (sizeof(T) == 8) {
+        return batch::build_tables<T, 64>(c, n, items, L, ws, fold);
+    } else {
+        const int lanes = kVariantsF32[variant].lanes;
+        if (lanes == 16) return batch::build_tables<T, 16>(c, n, items, L, ws, fold);
+        if (lanes == 32) return batch::build_tables<T, 32>(c, n, items, L, ws, fold);
+        return batch::build_tables<T, 64>(c, n, items, L, ws, fold);
+    }
 }
 
 template <class T>
@@ -923,18 +987,16 @@ int enqueue_batched_run(const mpdata_problem* c, int n, const batch::Tables<T>& 
     return MPDATA_OK;
 }
 
+// Host image of the tables in the workspace's table region, and the device
+// addresses of each table: donor[0], donor[1], pass[0][*], pass[1][*],
+// copyback, each in a slot of n entries of the largest entry type.
 template <class T>
-int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, int nsteps, int flags, void* ws,
-                hipStream_t st)
+void pack_tables(const mpdata_problem* c, int n, const batch::Tables<T>& tb, void* ws, std::vector<char>& host,
+                 BatchDev<T>& dv)
 {
-    const batch::Layout L = batch::layout(c, n, items);
-    const batch::Tables<T> tb = batch::build_tables<T>(c, n, items, L, (char*)ws);
-    // pack the tables: donor[0], donor[1], pass[0][*], pass[1][*], copyback
     const size_t slot = std::max(sizeof(mpdata::fused::BatchEntry<double>),
                                  std::max(sizeof(mpdata::stages::DonorEntry<double>),
                                           sizeof(mpdata::fused::DonorBlocks<double>))) * n;
-    std::vector<char> host(L.table_bytes, 0);
-    BatchDev<T> dv;
     size_t off = 0;
     auto put = [&](const void* src, size_t bytes) {
         memcpy(host.data() + off, src, bytes);
@@ -949,21 +1011,98 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
             dv.pass[par][m - 2] =
                 (const mpdata::fused::BatchEntry<T>*)put(tb.pass[par][m - 2].data(), sizeof(tb.pass[par][0][0]) * n);
     dv.copyback = (const mpdata::stages::DonorEntry<T>*)put(tb.copyback.data(), sizeof(tb.copyback[0]) * n);
+}
 
+// MPDATA_BATCH_VARIANT (environment, read per call): force a kernel variant
+// (0 .. variants - 1) instead of the tuned or default one.
+int forced_variant(int dtype)
+{
+    const char* e = getenv("MPDATA_BATCH_VARIANT");
+    if (!e || !*e) return -1;
+    const int v = atoi(e);
+    return v >= 0 && v < variant_count(dtype) ? v : -2;
+}
+
+template <class T>
+int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, int nsteps, int flags, void* ws,
+                hipStream_t st)
+{
+    const batch::Layout L = batch::layout(c, n, items);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(MPDATA_EDEVICE, "no current device");
-    char kb[160];
-    snprintf(kb, sizeof kb, "|dev%d|ws%p|s%d|f%d", dev, ws, nsteps, flags & MPDATA_BATCH_GRAPH);
-    std::string key = shape_key(c, n, items) + kb;
+
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    // kernel variant: forced, tuned (per batch shape), else the default (0)
+    const std::string skey = shape_key(c, n, items);
+    read_tune_file();
+    int variant = forced_variant(c->dtype);
+    if (variant == -2)
+        return fail(MPDATA_EINVAL, "MPDATA_BATCH_VARIANT names no variant of this dtype (0 .. %d)",
+                    variant_count(c->dtype) - 1);
+    std::vector<char> host(L.table_bytes, 0);
+    if (variant < 0) {
+        auto it = g_tuned.find(skey);
+        if (it != g_tuned.end() && it->second >= 0 && it->second < variant_count(c->dtype)) {
+            variant = it->second;
+        } else if ((flags & MPDATA_BATCH_TUNE) && variant_count(c->dtype) > 1) {
+            // time one step of each variant on the caller's data (a step of
+            // parity 0 reads the caller's fields and writes only workspace
+            // fields; tuning synchronises the stream)
+            struct Events {
+                hipEvent_t e[2] = {nullptr, nullptr};
+                ~Events()
+                {
+                    for (hipEvent_t x : e)
+                        if (x) (void)hipEventDestroy(x);
+                }
+            } ev;
+            if (hipEventCreate(&ev.e[0]) != hipSuccess || hipEventCreate(&ev.e[1]) != hipSuccess)
+                return fail(MPDATA_EDEVICE, "tuning events");
+            float best = 1e30f;
+            variant = 0;
+            for (int v = 0; v < variant_count(c->dtype); ++v) {
+                const batch::Tables<T> tv = tables_for<T>(c, n, items, L, (char*)ws, v);
+                BatchDev<T> dvv;
+                pack_tables<T>(c, n, tv, ws, host, dvv);
+                if (hipStreamSynchronize(st) != hipSuccess ||
+                    hipMemcpyAsync(ws, host.data(), L.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    return fail(MPDATA_EDEVICE, "tuning table upload");
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2; ++rep) {   // the first is a warm-up
+                    if (hipEventRecord(ev.e[0], st) != hipSuccess) return fail(MPDATA_EDEVICE, "tuning event record");
+                    if (int rc = enqueue_batched_step<T>(c, n, tv, dvv, 0, v, st)) return rc;
+                    if (hipEventRecord(ev.e[1], st) != hipSuccess || hipEventSynchronize(ev.e[1]) != hipSuccess ||
+                        hipEventElapsedTime(&ms, ev.e[0], ev.e[1]) != hipSuccess)
+                        return fail(MPDATA_EDEVICE, "tuning run failed");
+                }
+                if (ms < best) {
+                    best = ms;
+                    variant = v;
+                }
+            }
+            g_tuned[skey] = variant;
+            write_tune_file(skey, variant);
+        } else {
+            variant = 0;
+        }
+    }
+
+    const batch::Tables<T> tb = tables_for<T>(c, n, items, L, (char*)ws, variant);
+    BatchDev<T> dv;
+    pack_tables<T>(c, n, tb, ws, host, dv);
+
+    char kb[192];
+    snprintf(kb, sizeof kb, "|dev%d|ws%p|s%d|f%d|v%d|fold%d", dev, ws, nsteps, flags & MPDATA_BATCH_GRAPH, variant,
+             (int)tb.fold);
+    std::string key = skey + kb;
     for (int i = 0; i < n; ++i) {
         char pb[160];
         snprintf(pb, sizeof pb, "|%p,%p,%p,%p,%p", items[i].psi, items[i].cx, items[i].cy, items[i].cz, items[i].g);
         key += pb;
     }
-
-    std::lock_guard<std::mutex> lk(g_batch_mu);
     if (g_batch_cache.size() >= 16 && !g_batch_cache.count(key)) {
-        // bounded cache: retire every other entry once its last upload is done
+        // bounded cache: retire every entry once its last upload is done
         for (auto& kv : g_batch_cache) {
             BatchCacheEntry& old = kv.second;
             if (old.upload_done) {
@@ -989,47 +1128,6 @@ int run_batched(const mpdata_problem* c, int n, const mpdata_batch_item* items, 
     if (hipMemcpyAsync(ws, ce.pinned, L.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipEventRecord(ce.upload_done, st) != hipSuccess)
         return fail(MPDATA_EDEVICE, "batch table upload");
-
-    // kernel variant: tuned (per batch shape), else one workgroup per CU
-    const std::string skey = shape_key(c, n, items);
-    read_tune_file();
-    int variant = 0;
-    auto it = g_tuned.find(skey);
-    if (it != g_tuned.end()) {
-        variant = it->second;
-    } else if ((flags & MPDATA_BATCH_TUNE) && c->dtype == MPDATA_F32) {
-        struct Events {
-            hipEvent_t e[2] = {nullptr, nullptr};
-            ~Events()
-            {
-                for (hipEvent_t x : e)
-                    if (x) (void)hipEventDestroy(x);
-            }
-        } ev;
-        if (hipEventCreate(&ev.e[0]) != hipSuccess || hipEventCreate(&ev.e[1]) != hipSuccess)
-            return fail(MPDATA_EDEVICE, "tuning events");
-        float best = 1e30f;
-        for (int v = 0; v < 2; ++v) {
-            float ms = 0.0f;
-            for (int rep = 0; rep < 2; ++rep) {   // the first is a warm-up
-                if (hipEventRecord(ev.e[0], st) != hipSuccess) return fail(MPDATA_EDEVICE, "tuning event record");
-                if (int rc = enqueue_batched_step<T>(c, n, tb, dv, 0, v, st)) return rc;
-                if (hipEventRecord(ev.e[1], st) != hipSuccess || hipEventSynchronize(ev.e[1]) != hipSuccess ||
-                    hipEventElapsedTime(&ms, ev.e[0], ev.e[1]) != hipSuccess)
-                    return fail(MPDATA_EDEVICE, "tuning run failed");
-            }
-            if (ms < best) {
-                best = ms;
-                variant = v;
-            }
-        }
-        g_tuned[skey] = variant;
-        write_tune_file(skey, variant);
-    }
-    if (ce.variant >= 0 && ce.variant != variant && ce.exec) {
-        (void)hipGraphExecDestroy(ce.exec);
-        ce.exec = nullptr;
-    }
     ce.variant = variant;
 
     if (!(flags & MPDATA_BATCH_GRAPH)) return enqueue_batched_run<T>(c, n, tb, dv, nsteps, variant, st);
@@ -1108,8 +1206,16 @@ int ustep(const mpdata_umesh* m, const void* psi, void* out, const void* vn, con
     a.n_nodes = m->n_nodes;
     a.nz = m->nz;
     Timed tm(MPDATA_KERNEL_USTEP, st);
-    const unsigned blocks = (unsigned)(((m->n_nodes + 3) / 4 + 7) / 8 * 8);   // a wave per node, 8 | blocks
-    mpdata::unstructured::k_ustep<T><<<blocks, 256, 0, st>>>(a);
+    const char* mode = getenv("MPDATA_USTEP");
+    if (mode && strcmp(mode, "wave") == 0) {
+        const unsigned blocks = (unsigned)(((m->n_nodes + 3) / 4 + 7) / 8 * 8);   // a wave per node, 8 | blocks
+        mpdata::unstructured::k_ustep_wave<T><<<blocks, 256, 0, st>>>(a);
+    } else {
+        // 16 nodes per 256-thread block (four per wave), 8 | blocks
+        const int per_block = 4 * mpdata::unstructured::kNodesPerWave;
+        const unsigned blocks = (unsigned)(((m->n_nodes + per_block - 1) / per_block + 7) / 8 * 8);
+        mpdata::unstructured::k_ustep<T><<<blocks, 256, 0, st>>>(a);
+    }
     return launch_status("unstructured step");
 }
 

@@ -57,14 +57,17 @@ def test_batched_matches_oracle(dtype, iters, graph):
     steps = 5   # odd: the final state comes back through the copy kernel
     mp.run_batched(probs, steps, iters=iters, limiter=True, bc=(P, C, C), graph=graph)
     torch.cuda.synchronize()
-    tol = 1e-12 if dtype == "f64" else 3e-5
+    tol = 1e-12 if dtype == "f64" else 7e-7
+    worst = 0.0
     for (tr, cx, cy, cz, g), pr in zip(host, probs):
         nz, ny, nx = g.shape
         p = oracle.RefProblem(nx, ny, nz, bc=(P, C, C), iters=iters, limiter=True)
         got = pr["psi"].double().cpu().numpy()
         for t in range(tr.shape[0]):
             want = oracle.run(p, steps, tr[t], cx, cy, cz, g)
-            assert np.max(np.abs(got[t] - want)) <= tol * np.max(np.abs(want))
+            worst = max(worst, float(np.max(np.abs(got[t] - want)) / np.max(np.abs(want))))
+    _say(f"[batched]   worst rel err vs oracle {worst:.3e}")
+    assert worst <= tol
 
 
 def test_batched_equals_single_problem_path():
@@ -137,18 +140,120 @@ def test_graph_replays_match_eager():
             assert torch.equal(a["psi"], b["psi"]), rep
 
 
-def test_tuner_writes_cache(tmp_path, monkeypatch):
+# The batched kernel variants (FP32): tile row width x workgroups per CU x
+# donor-cell pass folded into the first corrective pass or separate.
+VARIANTS_F32 = [(32, 1, "fold"), (32, 2, "fold"), (64, 1, "fold"), (64, 2, "fold"), (16, 1, "fold"),
+                (16, 2, "fold"), (32, 1, "split"), (32, 2, "split"), (64, 1, "split"), (64, 2, "split"),
+                (16, 1, "split"), (16, 2, "split")]
+
+
+@pytest.mark.parametrize("variant", range(len(VARIANTS_F32)))
+@pytest.mark.parametrize("iters", [2, 3])
+def test_every_f32_variant_matches_oracle_and_single_path(variant, iters, monkeypatch):
+    """Each tile variant the tuner can pick, forced with MPDATA_BATCH_VARIANT:
+    every tracer against the FP64 oracle and against the single-problem path
+    (the same arithmetic per cell whatever the tile)."""
     torch = _torch()
     import paper_1908_06094_amd as mp
 
+    lanes, wgs, fold = VARIANTS_F32[variant]
+    _say(f"[batched] variant {variant} ({lanes} lanes, {wgs} workgroup(s) per CU, {fold}) iters={iters}")
+    monkeypatch.setenv("MPDATA_BATCH_VARIANT", str(variant))
+    probs, host = _batch("f32", seed=40 + variant)
+    single = []
+    for pr in probs:
+        outs = []
+        for t in range(pr["psi"].shape[0]):
+            x = pr["psi"][t].clone()
+            mp.run(x, pr["cx"], pr["cy"], pr["cz"], pr["g"], 3, iters=iters, limiter=True, bc=(P, C, C))
+            outs.append(x)
+        single.append(torch.stack(outs))
+    mp.run_batched(probs, 3, iters=iters, limiter=True, bc=(P, C, C), graph=(variant % 2 == 0))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (tr, cx, cy, cz, g), pr, r in zip(host, probs, single):
+        nz, ny, nx = g.shape
+        p = oracle.RefProblem(nx, ny, nz, bc=(P, C, C), iters=iters, limiter=True)
+        got = pr["psi"].double().cpu().numpy()
+        for t in range(tr.shape[0]):
+            want = oracle.run(p, 3, tr[t], cx, cy, cz, g)
+            worst = max(worst, float(np.max(np.abs(got[t] - want)) / np.max(np.abs(want))))
+        assert torch.max(torch.abs(pr["psi"] - r)).item() <= 1e-6 * torch.max(torch.abs(r)).item()
+    _say(f"[batched]   worst rel err vs oracle {worst:.3e}")
+    assert worst <= 7e-7
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_f64_variants_equal_single_path(variant, monkeypatch):
+    """FP64's two variants (donor-cell pass folded or separate) equal the
+    single-problem path bitwise; a third index is refused."""
+    torch = _torch()
+    import paper_1908_06094_amd as mp
+
+    probs, _ = _batch("f64", seed=50)
+    monkeypatch.setenv("MPDATA_BATCH_VARIANT", "2")
+    with pytest.raises(mp.MpdataError) as ei:
+        mp.run_batched(probs, 1, iters=2, graph=False)
+    assert "MPDATA_BATCH_VARIANT" in str(ei.value)
+    monkeypatch.setenv("MPDATA_BATCH_VARIANT", str(variant))
+    if variant == 1:
+        monkeypatch.setenv("MPDATA_KERNELS", "split")   # the single path's split layout
+    ref = []
+    for pr in probs:
+        outs = []
+        for t in range(pr["psi"].shape[0]):
+            x = pr["psi"][t].clone()
+            mp.run(x, pr["cx"], pr["cy"], pr["cz"], pr["g"], 3, iters=3, limiter=True, bc=(P, C, C))
+            outs.append(x)
+        ref.append(torch.stack(outs))
+    monkeypatch.delenv("MPDATA_KERNELS", raising=False)
+    mp.run_batched(probs, 3, iters=3, limiter=True, bc=(P, C, C), graph=False)
+    torch.cuda.synchronize()
+    for pr, r in zip(probs, ref):
+        assert torch.equal(pr["psi"], r)
+
+
+def _cache_lines(path):
+    return [ln.rstrip("\n").split("\t") for ln in open(path) if ln.strip()]
+
+
+def test_tuner_writes_cache(tmp_path, monkeypatch):
+    """Tuning times every variant on the batch, writes its choice (batch
+    shape, tab, variant) to the file MPDATA_TUNE_CACHE names, and reuses it;
+    a new cache path within the same process is read afresh (its file knows
+    nothing of this shape, so the batch is tuned again and the choice lands
+    in the new file)."""
+    torch = _torch()
+    import paper_1908_06094_amd as mp
+
+    monkeypatch.delenv("MPDATA_BATCH_VARIANT", raising=False)
     path = tmp_path / "tune.txt"
     monkeypatch.setenv("MPDATA_TUNE_CACHE", str(path))
     probs, _ = _batch("f32", seed=30)
     before = [pr["psi"].clone() for pr in probs]
     mp.run_batched(probs, 2, iters=2, graph=False, tune=True)
     torch.cuda.synchronize()
-    # the tuning step does not touch the fields; the run advanced them
+    # the tuning steps do not touch the fields; the run advanced them
     assert any(not torch.equal(a, b["psi"]) for a, b in zip(before, probs))
+    lines = _cache_lines(path)
+    assert len(lines) == 1, lines
+    key, variant = lines[0]
+    assert key.startswith("d1 i2 l1 b011 n%d;" % len(probs))
+    for nz, ny, nx, nt in SHAPES:
+        assert f"{nx}x{ny}x{nz}t{nt}" in key
+    assert 0 <= int(variant) < len(VARIANTS_F32)
+    _say(f"[batched] tuned variant {variant}: {VARIANTS_F32[int(variant)]}")
+    # the same shape again: answered from the cache, nothing appended
+    mp.run_batched(probs, 2, iters=2, graph=False, tune=True)
+    torch.cuda.synchronize()
+    assert len(_cache_lines(path)) == 1
+    # another cache file, same process
+    path2 = tmp_path / "tune2.txt"
+    monkeypatch.setenv("MPDATA_TUNE_CACHE", str(path2))
+    mp.run_batched(probs, 2, iters=2, graph=False, tune=True)
+    torch.cuda.synchronize()
+    lines2 = _cache_lines(path2)
+    assert len(lines2) == 1 and lines2[0][0] == key
 
 
 def test_64_problem_batch_sampled():
@@ -173,6 +278,8 @@ def test_64_problem_batch_sampled():
         for t in range(h["psi"].shape[0]):
             want = oracle.run(p, 20, h["psi"][t].astype(np.float64), *(h[k].astype(np.float64)
                                                                        for k in ("cx", "cy", "cz", "g")))
-            assert np.max(np.abs(got[t] - want)) <= 3e-5 * np.max(np.abs(want))
+            err = float(np.max(np.abs(got[t] - want)) / np.max(np.abs(want)))
+            _say(f"[batched]   problem {i} tracer {t}: rel err vs oracle {err:.3e}")
+            assert err <= 3e-6
     for pr in probs:
         assert float(pr["psi"].min()) >= 0.0
