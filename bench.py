@@ -303,18 +303,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def time_unstructured(mp, torch, dev, steps=20, cpu=True):
-    """The paper's own dwarf: the edge-based donor-cell step on an octahedral
-    grid of 70 144 nodes (O128: 209 864 edges) x 80 levels, FP64 (solid-body
-    winds through the dual faces, a zero vertical wind read all the same,
-    unit density, a cosine bell plus noise), `steps` steps."""
+def _urun_timed(mp, torch, dev, u, steps):
+    """Wall and mean kernel time of `steps` unstructured steps of workload u."""
     import numpy as np
 
-    from workloads import octahedral as octa
-
-    u = octa.octahedral_workload(128, 80)
-    m = u.mesh
-    dm = mp.DeviceMesh.from_octa(m, u.nz, pivbz=u.pivbz)
+    dm = mp.DeviceMesh.from_octa(u.mesh, u.nz, pivbz=u.pivbz)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     psi, vn, w, rho = t(u.psi), t(u.vn), t(u.w), t(u.rho)
     ws = torch.empty(u.points * 8 + 256, dtype=torch.uint8, device=dev)
@@ -327,7 +320,23 @@ def time_unstructured(mp, torch, dev, steps=20, cpu=True):
     wall = time.perf_counter() - t0
     mp.timing_enable(False)
     kms, kn = mp.timing_read(mp.MPDATA_KERNEL_USTEP)
-    avg_s = kms * 1e-3 / max(kn, 1)
+    return wall, kms * 1e-3 / max(kn, 1)
+
+
+def time_unstructured(mp, torch, dev, steps=20, cpu=True):
+    """The paper's own dwarf: the edge-based donor-cell step on an octahedral
+    grid of 70 144 nodes (O128: 209 864 edges) x 80 levels, FP64 (solid-body
+    winds through the dual faces, a zero vertical wind read all the same,
+    unit density, a cosine bell plus noise), `steps` steps; and the same
+    mesh with its nodes and edges numbered at random, against the row-by-row
+    numbering (the kernel and the arithmetic are the same; only the memory
+    locality of the gathers differs)."""
+    from workloads import octahedral as octa
+
+    u = octa.octahedral_workload(128, 80)
+    m = u.mesh
+    wall, avg_s = _urun_timed(mp, torch, dev, u, steps)
+    _, avg_r = _urun_timed(mp, torch, dev, octa.renumbered_workload(u), steps)
     # algorithmic traffic per step: read psi, w, rho and write psi per node
     # and level, read vn per edge and level (the edge fluxes and the vertical
     # fluxes stay on chip)
@@ -337,7 +346,9 @@ def time_unstructured(mp, torch, dev, steps=20, cpu=True):
            "ms_per_step": round(wall * 1e3 / steps, 4), "kernel_us": round(avg_s * 1e6, 2),
            "bytes_per_step": nbytes, "hbm_GBps": round(nbytes / avg_s / 1e9, 1),
            "hbm_frac": round(nbytes / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-           "table2_accesses_per_plane_fused": 5 * m.n_nodes}
+           "table2_accesses_per_plane_fused": 5 * m.n_nodes,
+           "numbering": {"row_by_row_kernel_us": round(avg_s * 1e6, 2), "random_kernel_us": round(avg_r * 1e6, 2),
+                         "random_over_row_by_row": round(avg_r / avg_s, 3)}}
     if cpu:
         import oracle
 

@@ -243,6 +243,7 @@ struct PassArgs {
     T* ruz;
     T* rbu;
     T* rbd;
+    T* rphi;   // REC with DONOR: psi^(1), the input iterate the pass forms
 };
 
 // Tile layout of the limited velocities that one pass hands to the next
@@ -540,6 +541,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                     }
                     phi_t = p - div_nr(((fxr_c - fxl) + (fyr_c - fyl)) + (fzr - fzl), R.g);
                     fz_d = fzr;
+                    if (REC && writer && t >= kb && t < ke) a.rphi[(long long)t * geo.sz + col] = phi_t;
                 } else {
                     phi_t = C.phi;
                 }

@@ -582,31 +582,40 @@ struct AdjRec {
     std::vector<double*> phis, ut, vl, bu, bd;
 };
 
-// One forward step through the recording kernels (the donor-cell pass, then
-// the fused corrective passes that also store their antidiffusive
-// velocities and beta), keeping the step's intermediates in R.  The
-// adjoint's forward sweep and its segment recomputations both take this
-// path, so a state is the same whatever the checkpoint interval.
-int step_record(const mpdata_problem* p, const double* psin, double* psout, const double* cx, const double* cy,
-                const double* cz, const double* gm, const AdjRec& R, hipStream_t st)
+// One forward step of the adjoint's sweeps, through the kernels of the
+// forward path: the first corrective pass carries the donor-cell pass (a
+// one-pass step is the donor-cell kernel alone), the passes hand on their
+// limited velocities.  With `record` the passes are the recording variants,
+// which also store psi^(1), each pass's antidiffusive velocities and beta:
+// the step's intermediates land in R.  The recording and the plain variants
+// evaluate the same arithmetic (they differ in stores only), so a state is
+// the same whatever steps were recorded and whatever the checkpoint
+// interval (tested bitwise).
+int step_adjoint_fwd(const mpdata_problem* p, const double* psin, double* psout, const double* cx, const double* cy,
+                     const double* cz, const double* gm, const AdjRec& R, bool record, hipStream_t st)
 {
     namespace F = mpdata::fused;
     const int M = p->iters;
-    mpdata::Geo g = geo_of(p);
-    dim3 blk(64, 4, 1);
-    dim3 dgrd((p->nx + 63) / 64, (p->ny + 3) / 4, (p->nz + F::kDonorChunk - 1) / F::kDonorChunk);
-    F::k_donor_march<double><<<dgrd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, M == 1 ? psout : R.phis[1]);
-    if (int rc = launch_status("adjoint: donor-cell pass")) return rc;
+    if (M == 1) {
+        mpdata::Geo g = geo_of(p);
+        dim3 blk(64, 4, 1);
+        dim3 dgrd((p->nx + 63) / 64, (p->ny + 3) / 4, (p->nz + F::kDonorChunk - 1) / F::kDonorChunk);
+        F::k_donor_march<double><<<dgrd, blk, 0, st>>>(g, psin, cx, cy, cz, gm, psout);
+        return launch_status("adjoint: donor-cell pass");
+    }
     F::PassArgs<double> a{};
     a.psin = psin;
     a.g = gm;
     a.eps = p->eps > 0.0 ? p->eps : 1e-15;
-    a.tiles_x = (p->nx + F::Tile<double>::tile_x - 1) / F::Tile<double>::tile_x;
     a.tiles_y = (p->ny + F::Tile<double>::tile_y - 1) / F::Tile<double>::tile_y;
     a.vel_tiled = 0;
     for (int m = 2; m <= M; ++m) {
-        a.phi = R.phis[m - 1];
-        a.out = m == M ? psout : R.phis[m];
+        const bool donor = m == 2, last = m == M;
+        const int tile_x = donor ? F::Tile<double>::donor_tile_x : F::Tile<double>::tile_x;
+        a.tiles_x = (p->nx + tile_x - 1) / tile_x;
+        a.phi = donor ? nullptr : R.phis[m - 1];
+        a.rphi = record && donor ? R.phis[1] : nullptr;
+        a.out = last ? psout : R.phis[m];
         a.u = m == 2 ? cx : R.vl[3 * (m - 1)];
         a.v = m == 2 ? cy : R.vl[3 * (m - 1) + 1];
         a.w = m == 2 ? cz : R.vl[3 * (m - 1) + 2];
@@ -618,8 +627,18 @@ int step_record(const mpdata_problem* p, const double* psin, double* psout, cons
         a.ruz = R.ut[3 * m + 2];
         a.rbu = R.bu[m];
         a.rbd = R.bd[m];
-        const int rc = p->limiter ? launch_pass<double, true, true, true>(p, a, st)
-                                  : launch_pass<double, false, true, true>(p, a, st);
+        int rc;
+        if (record) {
+            if (donor)
+                rc = p->limiter ? launch_pass<double, true, true, true, true>(p, a, st)
+                                : launch_pass<double, false, true, true, true>(p, a, st);
+            else
+                rc = p->limiter ? launch_pass<double, true, true, true>(p, a, st)
+                                : launch_pass<double, false, true, true>(p, a, st);
+        } else {
+            // the plain passes: the last one writes no velocities
+            rc = launch_corrective<double>(p, a, last, donor, st);
+        }
         if (rc) return rc;
     }
     return MPDATA_OK;
@@ -713,8 +732,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
             dst = s + 1 < nsteps ? seg[r + 1] : pp[0];
         else
             dst = (s + 1) % K == 0 ? ckpt[(s + 1) / K] : (cur == pp[0] ? pp[1] : pp[0]);
-        // before the last segment the records are scratch
-        if (int rc = step_record(p, cur, dst, cx, cy, cz, gm, rec[r >= 0 ? r : 0], st)) return rc;
+        // before the last segment no record is kept: the plain kernels
+        if (int rc = step_adjoint_fwd(p, cur, dst, cx, cy, cz, gm, rec[r >= 0 ? r : 0], r >= 0, st)) return rc;
         cur = dst;
     }
     if (psiT && cur != psiT) copy(psiT, cur);
@@ -732,8 +751,8 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
         // segment's are kept from the forward sweep)
         if (sg < L.segs - 1)
             for (int r = 0; r < s1 - s0; ++r)
-                if (int rc = step_record(p, state(r), r + 1 < s1 - s0 ? seg[r + 1] : sink, cx, cy, cz, gm, rec[r],
-                                         st))
+                if (int rc = step_adjoint_fwd(p, state(r), r + 1 < s1 - s0 ? seg[r + 1] : sink, cx, cy, cz, gm,
+                                              rec[r], true, st))
                     return rc;
         for (int r = s1 - s0 - 1; r >= 0; --r) {
             const AdjRec& R = rec[r];
@@ -1207,7 +1226,8 @@ int ustep(const mpdata_umesh* m, const void* psi, void* out, const void* vn, con
     a.nz = m->nz;
     Timed tm(MPDATA_KERNEL_USTEP, st);
     const char* mode = getenv("MPDATA_USTEP");
-    if (mode && strcmp(mode, "wave") == 0) {
+    const bool fits32 = (long long)m->n_nodes * m->nz < (1LL << 31) && (long long)m->n_edges * m->nz < (1LL << 31);
+    if (!fits32 || (mode && strcmp(mode, "wave") == 0)) {
         const unsigned blocks = (unsigned)(((m->n_nodes + 3) / 4 + 7) / 8 * 8);   // a wave per node, 8 | blocks
         mpdata::unstructured::k_ustep_wave<T><<<blocks, 256, 0, st>>>(a);
     } else {

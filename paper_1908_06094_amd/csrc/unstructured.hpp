@@ -73,8 +73,11 @@ __device__ __forceinline__ T ustep_point(const UArgs<T>& a, long long c, int k, 
     return a.psi[c + k] - div / a.rho[c + k];
 }
 
+// One wave per node (the former mapping, kept for comparison): the node's
+// connectivity is wave-uniform (scalar loads), the lanes run over the levels
+// in chunks of 64.
 template <class T>
-__global__ void __launch_bounds__(256) k_ustep(UArgs<T> a)
+__global__ void __launch_bounds__(256) k_ustep_wave(UArgs<T> a)
 {
     const int wg = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     const int n = __builtin_amdgcn_readfirstlane(wg * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -91,9 +94,6 @@ __global__ void __launch_bounds__(256) k_ustep(UArgs<T> a)
         if (k >= a.nz) break;
         const bool two = k2 < a.nz;
         const int kk2 = two ? k2 : k;   // a valid level for the second chunk's loads
-        // horizontal: signed sum of the node's edge fluxes (Listings 4-5, 8),
-        // in groups of kGroup edges whose loads are all issued before the
-        // group's fluxes are summed (in table order)
         T acc = T(0), acc2 = T(0);
         for (int jb = j0; jb < j1; jb += kGroup) {
             T f[kGroup], f2[kGroup], sg[kGroup];
@@ -119,6 +119,72 @@ __global__ void __launch_bounds__(256) k_ustep(UArgs<T> a)
         }
         a.out[c + k] = ustep_point(a, c, k, acc, rvol);
         if (two) a.out[c + k2] = ustep_point(a, c, k2, acc2, rvol);
+    }
+}
+
+// Four nodes per wave: each node takes a group of kLevelLanes lanes, which
+// run over its levels in blocks of kLevelLanes (one 128-byte line of FP64
+// per gather).  Every lane of the wave works on every level block (a column
+// of 80 levels fills 5 blocks exactly) and the four nodes' gathers are in
+// flight together.  A node's connectivity (up to kGroup edges: the edge's
+// and its two end nodes' element offsets and the sign) is read once, by
+// vector loads its group's lanes share, and kept in registers across the
+// level blocks; the offsets are 32-bit (the host uses the one-wave kernel
+// for meshes whose (node or edge) x level count reaches 2^31).  Edges are
+// summed in the node-to-edge table's order, as in the one-wave mapping.
+constexpr int kLevelLanes = 16;
+constexpr int kNodesPerWave = 64 / kLevelLanes;
+
+template <class T>
+__global__ void __launch_bounds__(256) k_ustep(UArgs<T> a)
+{
+    const int wg = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (kLevelLanes - 1);
+    const int n = (wg * (blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * kNodesPerWave + lane / kLevelLanes;
+    const bool node_ok = n < a.n_nodes;
+    const int nn = node_ok ? n : a.n_nodes - 1;   // every load stays in range
+    const int nz = a.nz;
+    const int c = nn * nz;
+    const int j0 = a.node_ptr[nn], j1 = a.node_ptr[nn + 1];
+    const T rvol = a.vol[nn];
+    int eo[kGroup], p1[kGroup], p2[kGroup];
+    T sg[kGroup];
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+        const int j = j0 + q < j1 ? j0 + q : j0;   // a valid entry (degree >= 1 where used)
+        const int e = j0 < j1 ? a.node_edges[j] : 0;
+        eo[q] = e * nz;
+        p1[q] = (j0 < j1 ? a.edge_nodes[2 * e] : nn) * nz;
+        p2[q] = (j0 < j1 ? a.edge_nodes[2 * e + 1] : nn) * nz;
+        sg[q] = j0 + q < j1 ? (T)a.node_sign[j] : T(0);
+    }
+    for (int k0 = 0; k0 < nz; k0 += kLevelLanes) {
+        const int k = k0 + sub;
+        const bool ok = node_ok && k < nz;
+        const int kk = k < nz ? k : nz - 1;
+        T f[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            f[q] = T(0);
+            if (j0 + q < j1) {
+                const T v = a.vn[eo[q] + kk];
+                f[q] = upos(v) * a.psi[p1[q] + kk] + uneg(v) * a.psi[p2[q] + kk];
+            }
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q)
+            if (j0 + q < j1) acc += sg[q] * f[q];
+        // nodes of a higher degree than kGroup (none on the octahedral grid)
+        for (int j = j0 + kGroup; j < j1; ++j) {
+            const long long e = a.node_edges[j];
+            const long long ip1 = a.edge_nodes[2 * e], ip2 = a.edge_nodes[2 * e + 1];
+            const T v = a.vn[e * nz + kk];
+            acc += (T)a.node_sign[j] * (upos(v) * a.psi[ip1 * nz + kk] + uneg(v) * a.psi[ip2 * nz + kk]);
+        }
+        const T r = ustep_point(a, (long long)c, kk, acc, rvol);
+        if (ok) a.out[c + k] = r;
     }
 }
 

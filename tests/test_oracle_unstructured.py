@@ -121,3 +121,19 @@ def test_rejects_bad_connectivity():
     bad[0, 0] = m.n_nodes
     with pytest.raises(ValueError):
         oracle.ustep(bad, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, f, np.zeros((m.n_edges, nz)), f, f)
+
+
+def test_renumbered_mesh_gives_the_same_step():
+    """The same octahedral mesh with nodes and edges numbered at random (the
+    unstructured numbering the benchmark compares with the row-by-row one):
+    the step gives every node the same value up to the order of its edge
+    sum (the oracle sums a node's edges in table order)."""
+    u = octa.random_uproblem(6, 5, seed=3, pivbz=0.5)
+    r = octa.renumbered_workload(u, 11)
+    _, (node_perm, edge_perm) = octa.renumbered(u.mesh, 11)
+    assert sorted(node_perm) == list(range(u.mesh.n_nodes)) and sorted(edge_perm) == list(range(u.mesh.n_edges))
+    m, mr = u.mesh, r.mesh
+    a = oracle.ustep(m.edges, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, u.psi, u.vn, u.w, u.rho, u.pivbz)
+    b = oracle.ustep(mr.edges, mr.node_ptr, mr.node_edges, mr.node_sign, mr.dual_volume, r.psi, r.vn, r.w, r.rho,
+                     r.pivbz)
+    assert np.max(np.abs(b - a[node_perm])) <= 1e-15 * np.max(np.abs(a))

@@ -233,3 +233,40 @@ def random_uproblem(N: int, nz: int, seed: int, courant: float = 0.4, pivbz: flo
     rho = rng.uniform(0.8, 1.2, size=(mesh.n_nodes, nz))
     psi = rng.uniform(0.0, 1.0, size=(mesh.n_nodes, nz))
     return UWorkload(f"random-O{N}-{nz}", mesh, nz, psi, vn, w, rho, pivbz)
+
+
+def renumbered(mesh: OctaMesh, seed: int):
+    """The same mesh with its nodes and edges numbered in a random order (an
+    unstructured numbering, against the row-by-row one of `build`).  Returns
+    the new mesh and (node_perm, edge_perm): new node i is old node
+    node_perm[i], new edge e is old edge edge_perm[e].  Each edge keeps its
+    orientation (ip1 -> ip2), so fluxes and their signs carry over; a node's
+    edges are listed in ascending new edge number."""
+    rng = np.random.default_rng(seed)
+    nn, ne = mesh.n_nodes, mesh.n_edges
+    node_perm = rng.permutation(nn)
+    edge_perm = rng.permutation(ne)
+    new_of_node = np.empty(nn, dtype=np.int64)
+    new_of_node[node_perm] = np.arange(nn)
+    edges = new_of_node[mesh.edges[edge_perm].astype(np.int64)].astype(np.int32)
+    inc = [[] for _ in range(nn)]
+    for e, (a, b) in enumerate(edges):
+        inc[a].append((e, 1))
+        inc[b].append((e, -1))
+    node_ptr = np.zeros(nn + 1, dtype=np.int32)
+    node_ptr[1:] = np.cumsum([len(x) for x in inc])
+    node_edges = np.array([e for x in inc for e, _ in sorted(x)], dtype=np.int32)
+    node_sign = np.array([s for x in inc for _, s in sorted(x)], dtype=np.int8)
+    out = OctaMesh(mesh.N, mesh.lat[node_perm], mesh.lon[node_perm], mesh.row_start, edges,
+                   mesh.edge_faces[edge_perm], mesh.faces, mesh.face_area, mesh.face_centroid, node_ptr,
+                   node_edges, node_sign, mesh.dual_volume[node_perm])
+    return out, (node_perm, edge_perm)
+
+
+def renumbered_workload(u: UWorkload, seed: int = 7) -> UWorkload:
+    """Workload u on its mesh with nodes and edges numbered at random (fields
+    permuted to match)."""
+    mesh, (np_, ep) = renumbered(u.mesh, seed)
+    return UWorkload(u.name + "-renumbered", mesh, u.nz, np.ascontiguousarray(u.psi[np_]),
+                     np.ascontiguousarray(u.vn[ep]), np.ascontiguousarray(u.w[np_]),
+                     np.ascontiguousarray(u.rho[np_]), u.pivbz)
