@@ -294,14 +294,14 @@ struct Slots {
     T fy[2][kRows][kLanes];
 };
 
-// The pass that also runs the donor-cell pass (DONOR) needs three more
-// plane slots: psi^n of the current plane and of the next (ring by plane
-// parity; the y neighbours of the donor-cell fluxes) and the donor-cell y
-// flux at each row's upper face, which the row above reads.
+// The pass that also runs the donor-cell pass (DONOR) needs four more plane
+// slots: psi^n and Cy of the current plane and of the next (rings by plane
+// parity), published one march step ahead of their use, from which each row
+// forms the donor-cell fluxes through its upper and its lower y face.
 template <class T, int L = DefaultLanes<T>::value>
 struct SlotsDonor : Slots<T, L> {
     T psd[2][Tile<T, L>::rows][L];
-    T fyd[Tile<T, L>::rows][L];
+    T cyd[2][Tile<T, L>::rows][L];
 };
 
 // One column's values of one plane: the loaded fields and what is derived
@@ -334,9 +334,10 @@ struct Raw {
 // DONOR: the pass is the first corrective pass of a step and forms its input
 // iterate psi^(1) itself, by the donor-cell pass on psi^n with the Courant
 // numbers (a.u, a.v, a.w), plane by plane ahead of its use (a.phi is not
-// read).  psi^n is loaded one plane ahead of the other fields and published
-// to LDS for the y neighbours; an extra march phase and barrier exchange the
-// donor-cell y fluxes; the row-end lanes and the outer rows load their
+// read).  psi^n and Cy are loaded one plane ahead of the other fields and
+// published to LDS, so that each row forms the donor-cell fluxes through
+// both of its y faces from its own and its neighbours' values without a
+// further barrier; the row-end lanes and the outer rows load their
 // neighbours beyond the tile.  Per cell the pass then reads psi^n, Cx, Cy,
 // Cz and G once: the step's separate donor-cell pass and its psi^(1) round
 // trip through HBM disappear.
@@ -410,12 +411,18 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             if (!DONOR) B.phi = a.phi[q];
             if (LIMIT && !DONOR) B.psin = a.psin[q];
             B.u = a.u[qv];
-            B.v = a.v[qv];
             B.w = *(has_w ? a.w + qv : a.g + q);
             B.g = a.g[q];
             if (DONOR) {
-                // psi^n one plane ahead (the donor-cell pass of plane k needs k+1)
-                B.psin = a.psin[(long long)map_index(k + 1, geo.nz, geo.closed_z) * geo.sz + col];
+                // psi^n and Cy one plane ahead (the donor-cell pass of plane k
+                // needs psi^n of k+1; Cy goes to LDS a step before its use)
+                const long long q1 = (long long)map_index(k + 1, geo.nz, geo.closed_z) * geo.sz + col;
+                B.psin = a.psin[q1];
+                B.v = a.v[q1];
+            } else {
+                B.v = a.v[qv];
+            }
+            if (DONOR) {
                 if (kXEdgeLoads) {
                     if (x_lo || x_hi) B.xe = a.psin[pl + col_xe];
                     if (x_lo) B.cxl = a.u[pl + col_xe];
@@ -478,19 +485,29 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             vmem_wait_all();
             flush(t - 1);
             // ---------------- DONOR: psi^(1) of plane t by the donor-cell pass ----------------
-            T phi_t, psin_n;
+            T phi_t, psin_n, v_t;
             if constexpr (DONOR) {
                 // plane t is the grid plane ck; virtual planes beyond a closed
                 // top repeat plane nz-1, whose psi^(1) the previous step formed
                 const int ck = map_index(t, geo.nz, geo.closed_z);
                 const bool repeat_top = geo.closed_z && t >= geo.nz;
                 const int sd = t & 1;
-                const T p = S.psd[sd][row][lane];       // psi^n of plane ck, published one step ago
-                S.psd[sd ^ 1][row][lane] = R.psin;       // psi^n of plane t+1, for the next step
+                // psi^n and Cy of plane ck, published one step ago; those of
+                // plane t+1 for the next step
+                const T p = S.psd[sd][row][lane];
+                v_t = S.cyd[sd][row][lane];
+                S.psd[sd ^ 1][row][lane] = R.psin;
+                S.cyd[sd ^ 1][row][lane] = R.v;
+                // the donor-cell flux through the upper y face of row r (the
+                // same operands, in the same order, for every row that forms it)
+                auto fy_row = [&](int r, int gr) __attribute__((always_inline)) {
+                    const T vr = wall_face(gr, geo.ny, geo.closed_y) ? zero : S.cyd[sd][r][lane];
+                    return pos_f(vr) * S.psd[sd][r][lane] + neg_f(vr) * S.psd[sd][r + 1][lane];
+                };
                 T fxr = zero, fyr = zero, fzr = zero;
                 if (!repeat_top) {
                     const T U = xwall ? zero : R.u;
-                    const T V = ywall ? zero : R.v;
+                    const T V = ywall ? zero : v_t;
                     const T W = (!has_w || wall_face(ck, geo.nz, geo.closed_z)) ? zero : R.w;
                     const T p_xn = lane_next(p);
                     const T p_xr = (kXEdgeLoads && x_hi) ? R.xe : p_xn;
@@ -503,15 +520,16 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                     fxr = pos_f(U) * p + neg_f(U) * p_xr;
                     fyr = pos_f(V) * p + neg_f(V) * p_yr;
                     fzr = pos_f(W) * p + neg_f(W) * p_zr;
-                    S.fyd[row][lane] = fyr;
-                }
-                lds_barrier();
-                if (!repeat_top) {
                     const T cxl = xwall_l ? zero : R.cxl;
-                    const T cyd = ywall_d ? zero : R.cyd;
                     const T fxl_n = lane_prev(fxr);
                     T fxl = (kXEdgeLoads && x_lo) ? pos_f(cxl) * R.xe + neg_f(cxl) * p : fxl_n;
-                    T fyl = (kOuterRows && y_lo) ? pos_f(cyd) * R.yx + neg_f(cyd) * p : S.fyd[dn][lane];
+                    T fyl;
+                    if (kOuterRows && y_lo) {
+                        const T cyd = ywall_d ? zero : R.cyd;
+                        fyl = pos_f(cyd) * R.yx + neg_f(cyd) * p;
+                    } else {
+                        fyl = fy_row(dn, gj - 1);   // the row below's upper face
+                    }
                     const T fzl = (geo.closed_z && ck == 0) ? zero : fz_d;
                     // A cell beyond a closed wall carries, by the halo rule,
                     // psi^(1) of the boundary cell it is clamped to: its loads
@@ -520,11 +538,11 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
                     T fxr_c = fxr, fyr_c = fyr;
                     if (y_virtual) {
                         if (gj < 0) {
-                            fyr_c = S.fyd[row - gj][lane];
+                            fyr_c = fy_row(row - gj, 0);
                             fyl = zero;
                         } else {
                             fyr_c = zero;
-                            fyl = geo.ny >= 2 ? S.fyd[row - (gj - (geo.ny - 2))][lane] : zero;
+                            fyl = geo.ny >= 2 ? fy_row(row - (gj - (geo.ny - 2)), geo.ny - 2) : zero;
                         }
                     }
                     if (x_edge_tile) {   // uniform over the workgroup: the tile touches a closed x wall
@@ -549,11 +567,12 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             } else {
                 phi_t = R.phi;
                 psin_n = R.psin;
+                v_t = R.v;
             }
             // ---------------- phase 0: plane t arrives ----------------
             N.phi = phi_t;
             N.u = xwall ? zero : R.u;
-            N.v = ywall ? zero : R.v;
+            N.v = ywall ? zero : v_t;
             N.w = (!has_w || wall_face(t, geo.nz, geo.closed_z)) ? zero : R.w;
             N.g = R.g;
             load(t + 1 <= t_last ? t + 1 : t_last, R);   // prefetch the next plane (unconditionally)
@@ -731,6 +750,7 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
             const int c0 = map_index(t0, geo.nz, geo.closed_z);
             const T p0 = a.psin[(long long)c0 * geo.sz + col];
             S.psd[t0 & 1][row][lane] = p0;
+            S.cyd[t0 & 1][row][lane] = a.v[(long long)c0 * geo.sz + col];
             fz_d = zero;
             if (!(geo.closed_z && c0 == 0)) {
                 const int cm = map_index(c0 - 1, geo.nz, geo.closed_z);
