@@ -477,6 +477,64 @@ __global__ void __launch_bounds__(256) k_adj_donor_limit_beta(
 // ---------------------------------------------------------------------------
 constexpr int kSlots = 7;
 
+// Kernel 1's work at the face c + 1/2 along axis a, given the adjoint lam of
+// its antidiffusive velocity: the seven slot values (s), lambda dU~/dU (ldu)
+// and lambda dU~/dpL (returned).  False (and nothing set) at a closed wall.
+__device__ __forceinline__ bool antidiff1_face(const Geo& g, const Cell& c, int a, double eps,
+                                               const double* __restrict__ phi, const double* const (&vel)[3],
+                                               const double* __restrict__ gm, double lam, double (&s)[kSlots],
+                                               double& ldu, double& own)
+{
+    const long long fo = face_idx(g, a, c.i, c.j, c.k);   // c.q when valid
+    if (fo < 0) return false;
+    int R[3] = {c.i, c.j, c.k};
+    R[a] += 1;
+    const double pL = phi[c.q], pR = phi[at(g, R[0], R[1], R[2])];
+    const double D0 = (pR + pL) + eps;
+    const double rD0 = rcp_nr(D0);
+    const double A = (pR - pL) * rD0;
+    double B[2], Vb[2], rDt[2], Sp[2], Sm[2];
+    int sidx = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (t == a) continue;
+        int Lp[3] = {c.i, c.j, c.k}, Rp[3] = {R[0], R[1], R[2]};
+        int Lm[3] = {c.i, c.j, c.k}, Rm[3] = {R[0], R[1], R[2]};
+        Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
+        Sp[sidx] = phi[at(g, Rp[0], Rp[1], Rp[2])] + phi[at(g, Lp[0], Lp[1], Lp[2])];
+        Sm[sidx] = phi[at(g, Rm[0], Rm[1], Rm[2])] + phi[at(g, Lm[0], Lm[1], Lm[2])];
+        rDt[sidx] = rcp_nr((Sp[sidx] + Sm[sidx]) + eps);
+        B[sidx] = 0.5 * ((Sp[sidx] - Sm[sidx]) * rDt[sidx]);
+        const long long f0 = face_idx(g, t, c.i, c.j, c.k), f1 = face_idx(g, t, R[0], R[1], R[2]);
+        const long long f2 = face_idx(g, t, Lm[0], Lm[1], Lm[2]), f3 = face_idx(g, t, Rm[0], Rm[1], Rm[2]);
+        const double* vt = vel[t];
+        const double v0 = (f0 < 0 || !vt) ? 0.0 : vt[f0], v1 = (f1 < 0 || !vt) ? 0.0 : vt[f1];
+        const double v2 = (f2 < 0 || !vt) ? 0.0 : vt[f2], v3 = (f3 < 0 || !vt) ? 0.0 : vt[f3];
+        Vb[sidx] = 0.25 * ((v0 + v1) + (v2 + v3));
+        ++sidx;
+    }
+    const double rGf = rcp_nr(0.5 * (gm[c.q] + gm[at(g, R[0], R[1], R[2])]));
+    const double U = vel[a] ? vel[a][fo] : 0.0;
+    const double S = (Vb[0] * B[0]) + (Vb[1] * B[1]);
+    const double dU = (sgn(U) - 2.0 * U * rGf) * A - S * rGf;
+    const double dA = (U < 0.0 ? -U : U) - (U * U) * rGf;
+    const double dS = -U * rGf;
+    const double gA = lam * dA;
+    const double r2 = rD0 * rD0;
+    s[0] = gA * (2.0 * pL + eps) * r2;
+    own = -(gA * (2.0 * pR + eps) * r2);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double gB = lam * dS * Vb[q];
+        const double rt2 = rDt[q] * rDt[q];
+        s[1 + 2 * q] = gB * (0.5 * (2.0 * Sm[q] + eps) * rt2);
+        s[2 + 2 * q] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
+        s[5 + q] = 0.25 * (lam * dS * B[q]);
+    }
+    ldu = lam * dU;
+    return true;
+}
+
 // Kernel 1's work at one cell, given the adjoints lam of the antidiffusive
 // velocities at its three own faces; returns lambda dU~/dpL summed over them.
 __device__ __forceinline__ double antidiff1_cell(const Geo& g, const Cell& c, double eps, const double* __restrict__ phi,
@@ -486,66 +544,24 @@ __device__ __forceinline__ double antidiff1_cell(const Geo& g, const Cell& c, do
                                                  long long field, double* __restrict__ lu, double* __restrict__ lv,
                                                  double* __restrict__ lw, bool assign_vel)
 {
-    const double* vel[3] = {u, v, w};
+    const double* const vel[3] = {u, v, w};
     double* lvel[3] = {lu, lv, lw};
     double own = 0.0;   // lambda dU~/dpL of the cell's three faces
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double* s = slots + (long long)a * kSlots * field + c.q;
-        const long long fo = face_idx(g, a, c.i, c.j, c.k);   // c.q when valid
-        if (fo < 0) {
-            for (int e = 0; e < kSlots; ++e) s[e * field] = 0.0;
+        double* sp = slots + (long long)a * kSlots * field + c.q;
+        double s[kSlots], ldu, own_a;
+        if (!antidiff1_face(g, c, a, eps, phi, vel, gm, lam_face[a], s, ldu, own_a)) {
+            for (int e = 0; e < kSlots; ++e) sp[e * field] = 0.0;
             if (lvel[a] && assign_vel) lvel[a][c.q] = 0.0;   // a closed wall's unused slot
             continue;
         }
-        int R[3] = {c.i, c.j, c.k};
-        R[a] += 1;
-        const double lam = lam_face[a];
-        const double pL = phi[c.q], pR = phi[at(g, R[0], R[1], R[2])];
-        const double D0 = (pR + pL) + eps;
-        const double rD0 = rcp_nr(D0);
-        const double A = (pR - pL) * rD0;
-        double B[2], Vb[2], rDt[2], Sp[2], Sm[2];
-        int sidx = 0;
+        own += own_a;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            if (t == a) continue;
-            int Lp[3] = {c.i, c.j, c.k}, Rp[3] = {R[0], R[1], R[2]};
-            int Lm[3] = {c.i, c.j, c.k}, Rm[3] = {R[0], R[1], R[2]};
-            Lp[t] += 1; Rp[t] += 1; Lm[t] -= 1; Rm[t] -= 1;
-            Sp[sidx] = phi[at(g, Rp[0], Rp[1], Rp[2])] + phi[at(g, Lp[0], Lp[1], Lp[2])];
-            Sm[sidx] = phi[at(g, Rm[0], Rm[1], Rm[2])] + phi[at(g, Lm[0], Lm[1], Lm[2])];
-            rDt[sidx] = rcp_nr((Sp[sidx] + Sm[sidx]) + eps);
-            B[sidx] = 0.5 * ((Sp[sidx] - Sm[sidx]) * rDt[sidx]);
-            const long long f0 = face_idx(g, t, c.i, c.j, c.k), f1 = face_idx(g, t, R[0], R[1], R[2]);
-            const long long f2 = face_idx(g, t, Lm[0], Lm[1], Lm[2]), f3 = face_idx(g, t, Rm[0], Rm[1], Rm[2]);
-            const double* vt = vel[t];
-            const double v0 = (f0 < 0 || !vt) ? 0.0 : vt[f0], v1 = (f1 < 0 || !vt) ? 0.0 : vt[f1];
-            const double v2 = (f2 < 0 || !vt) ? 0.0 : vt[f2], v3 = (f3 < 0 || !vt) ? 0.0 : vt[f3];
-            Vb[sidx] = 0.25 * ((v0 + v1) + (v2 + v3));
-            ++sidx;
-        }
-        const double rGf = rcp_nr(0.5 * (gm[c.q] + gm[at(g, R[0], R[1], R[2])]));
-        const double U = vel[a] ? vel[a][fo] : 0.0;
-        const double S = (Vb[0] * B[0]) + (Vb[1] * B[1]);
-        const double dU = (sgn(U) - 2.0 * U * rGf) * A - S * rGf;
-        const double dA = (U < 0.0 ? -U : U) - (U * U) * rGf;
-        const double dS = -U * rGf;
-        const double gA = lam * dA;
-        const double r2 = rD0 * rD0;
-        s[0 * field] = gA * (2.0 * pL + eps) * r2;
-        own += -(gA * (2.0 * pR + eps) * r2);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const double gB = lam * dS * Vb[q];
-            const double rt2 = rDt[q] * rDt[q];
-            s[(1 + 2 * q) * field] = gB * (0.5 * (2.0 * Sm[q] + eps) * rt2);
-            s[(2 + 2 * q) * field] = gB * (-0.5 * (2.0 * Sp[q] + eps) * rt2);
-            s[(5 + q) * field] = 0.25 * (lam * dS * B[q]);
-        }
+        for (int e = 0; e < kSlots; ++e) sp[e * field] = s[e];
         if (lvel[a]) {
-            if (assign_vel) lvel[a][fo] = lam * dU;
-            else lvel[a][fo] += lam * dU;
+            if (assign_vel) lvel[a][c.q] = ldu;
+            else lvel[a][c.q] += ldu;
         }
     }
     return own;
@@ -661,9 +677,12 @@ __device__ __forceinline__ double adj_antidiff_general_axis(const Geo& g, const 
 }
 
 // 6 waves per SIMD: 80 VGPRs with no spills (unbounded it takes 82, 5 waves)
+// general_only: only the cells of the general path (the k-marching kernel
+// of adjoint_march.hpp has gathered the others).
 __global__ void __launch_bounds__(256, 6) k_adj_antidiff2(Geo g, const double* __restrict__ slots, long long field,
                                                        double* __restrict__ lphi, double* __restrict__ lu,
-                                                       double* __restrict__ lv, double* __restrict__ lw)
+                                                       double* __restrict__ lv, double* __restrict__ lw,
+                                                       int general_only)
 {
     Cell c;
     if (!cell_of_thread(g, c)) return;
@@ -681,6 +700,7 @@ __global__ void __launch_bounds__(256, 6) k_adj_antidiff2(Geo g, const double* _
         fast = fast && (closed(g, b) ? (cb >= 2 && cb <= n - 3) : n >= 4);
     }
     if (fast) {
+        if (general_only) return;
         const long long st[3] = {1, g.sy, g.sz};
         const int cc[3] = {c.i, c.j, c.k};
         // offset of x - o along axis b (periodic wrap; closed axes are interior here)

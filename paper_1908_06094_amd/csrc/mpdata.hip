@@ -23,6 +23,7 @@
 #include "fused.hpp"
 #include "donor.hpp"
 #include "adjoint.hpp"
+#include "adjoint_march.hpp"
 #include "batched.hpp"
 #include "unstructured.hpp"
 
@@ -644,6 +645,16 @@ int step_adjoint_fwd(const mpdata_problem* p, const double* psin, double* psout,
     return MPDATA_OK;
 }
 
+// MPDATA_ADJOINT=march: the antidiffusive-velocity adjoint of a limited
+// pass as one k-marching kernel (adjoint_march.hpp) instead of its two
+// gather kernels with the slot fields in HBM; the results are the same bit
+// for bit.
+bool use_adjoint_march()
+{
+    const char* e = getenv("MPDATA_ADJOINT");
+    return e && strcmp(e, "march") == 0;
+}
+
 int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, const double* cx, const double* cy,
                 const double* cz, const double* gm, const double* seed, double* dpsi0, double* dcx, double* dcy,
                 double* dcz, double* psiT, void* ws, hipStream_t st)
@@ -716,6 +727,7 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
     const double* C3[3] = {cx, cy, cz};
     double* dC[3] = {dcx, dcy, dcz_t};
     Timed tm(MPDATA_KERNEL_STAGE, st);
+    const bool march = use_adjoint_march();
 
     // forward sweep: psi^{cK} into checkpoint c, other states ping-pong
     // between two scratch fields (the adjoint ones, unused until the
@@ -776,18 +788,57 @@ int adjoint_run(const mpdata_problem* p, int nsteps, int K, const double* psi0, 
                                                         lv[2], 1, m == M);
                 double* tgt[3];
                 for (int a = 0; a < 3; ++a) tgt[a] = m == 2 ? dC[a] : lvp[a];
-                if (p->limiter)
-                    // the limiter's in / out and bounds gather fused with the
-                    // antidiffusive velocities' first adjoint kernel
-                    A::k_adj_inout_bounds_antidiff1<<<grd, blk, 0, st>>>(
-                        g, eps, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx, lmn, lut[0], lut[1], lut[2], lpsin,
-                        m == M, prev[0], prev[1], prev[2], gm, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2],
-                        m > 2);
-                else   // unlimited: dJ/dU~ = dJ/dV
-                    A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lv[0],
-                                                            lv[1], lv[2], slots, slot_stride, lprev, tgt[0], tgt[1],
-                                                            tgt[2], m > 2);
-                A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2]);
+                if (p->limiter && march) {
+                    // the limiter's in / out and bounds gather and the
+                    // antidiffusive velocities' adjoint in one k-marching
+                    // kernel; the cells near closed ends are gathered after
+                    A::MarchArgs ma{};
+                    ma.eps = eps;
+                    ma.phi = ph;
+                    ma.ut = U3[0];
+                    ma.vt = U3[1];
+                    ma.wt = U3[2];
+                    ma.lin = lin;
+                    ma.lout = lout;
+                    ma.lmx = lmx;
+                    ma.lmn = lmn;
+                    ma.code = code[m];
+                    ma.lutx = lut[0];
+                    ma.luty = lut[1];
+                    ma.lutz = lut[2];
+                    ma.pu = prev[0];
+                    ma.pv = prev[1];
+                    ma.pw = prev[2];
+                    ma.gm = gm;
+                    ma.lpsin = lpsin;
+                    ma.slots = slots;
+                    ma.field = slot_stride;
+                    ma.lphi = lprev;
+                    ma.lu = tgt[0];
+                    ma.lv = tgt[1];
+                    ma.lw = tgt[2];
+                    ma.assign_psin = m == M;
+                    ma.assign_vel = m > 2;
+                    ma.tiles_x = (p->nx + A::kMTileX - 1) / A::kMTileX;
+                    ma.tiles_y = (p->ny + A::kMTileY - 1) / A::kMTileY;
+                    const int mgrid = pass_grid((long long)ma.tiles_x * ma.tiles_y * p->nz);
+                    A::k_adj_antidiff_march<<<mgrid, A::kMThreads, 0, st>>>(g, ma);
+                    A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2], 1);
+                } else {
+                    if (p->limiter)
+                        // the limiter's in / out and bounds gather fused with the
+                        // antidiffusive velocities' first adjoint kernel
+                        A::k_adj_inout_bounds_antidiff1<<<grd, blk, 0, st>>>(
+                            g, eps, ph, U3[0], U3[1], U3[2], lin, lout, code[m], lmx, lmn, lut[0], lut[1], lut[2],
+                            lpsin, m == M, prev[0], prev[1], prev[2], gm, slots, slot_stride, lprev, tgt[0], tgt[1],
+                            tgt[2], m > 2);
+                    else   // unlimited: dJ/dU~ = dJ/dV
+                        A::k_adj_antidiff1<<<grd, blk, 0, st>>>(g, eps, ph, prev[0], prev[1], prev[2], gm, lv[0],
+                                                                lv[1], lv[2], slots, slot_stride, lprev, tgt[0],
+                                                                tgt[1], tgt[2], m > 2);
+                    A::k_adj_antidiff2<<<grd, blk, 0, st>>>(g, slots, slot_stride, lprev, tgt[0], tgt[1], tgt[2],
+                                                            0);
+                }
                 std::swap(lcur, lprev);
                 for (int a = 0; a < 3; ++a) std::swap(lv[a], lvp[a]);
             }

@@ -68,6 +68,34 @@ def test_adjoint_matches_oracle(shape, bc, iters, lim, steps, k):
     assert np.max(np.abs(got[4].cpu().numpy() - out)) <= 1e-12 * np.max(np.abs(out))
 
 
+@pytest.mark.parametrize("shape,bc,iters,steps,k", [
+    ((9, 40, 70), (P, C, C), 2, 3, 2),     # several tiles in x and y, ragged ends
+    ((8, 33, 95), (P, P, P), 3, 2, 1),     # all periodic: every cell on the k-marching path
+    ((7, 23, 31), (C, C, C), 3, 2, 0),     # all closed: general-path bands on every side
+    ((5, 4, 4), (P, P, P), 2, 2, 1),       # the smallest periodic extents of the fast path
+    ((6, 3, 33), (P, P, C), 2, 2, 1),      # a periodic axis of 3 cells: every cell general
+    ((60, 128, 256), (P, C, C), 2, 2, 1),  # the configured grid
+])
+def test_adjoint_march_equals_gather_kernels(shape, bc, iters, steps, k, monkeypatch):
+    """The antidiffusive-velocity adjoint of a limited pass as one k-marching
+    kernel (MPDATA_ADJOINT=march) gives the same gradients, bit for bit, as
+    its two gather kernels with the slot fields in HBM."""
+    torch = _torch()
+    import paper_1908_06094_amd as mp
+
+    _say(f"[adjoint-march] shape={shape} bc={bc} iters={iters} steps={steps} k={k}")
+    psi, cx, cy, cz, g = workloads.random_problem(shape, bc, seed=7 + sum(shape), courant=0.8)
+    args = [_dev(a) for a in (psi, cx, cy, cz, g)]
+    seed = _dev(np.random.default_rng(4).uniform(-1, 1, size=shape))
+    monkeypatch.delenv("MPDATA_ADJOINT", raising=False)
+    want = mp.adjoint(*args, seed, steps, checkpoint_every=k, iters=iters, limiter=True, bc=bc)
+    monkeypatch.setenv("MPDATA_ADJOINT", "march")
+    got = mp.adjoint(*args, seed, steps, checkpoint_every=k, iters=iters, limiter=True, bc=bc)
+    torch.cuda.synchronize()
+    for which in range(5):
+        assert torch.equal(got[which], want[which]), which
+
+
 def test_adjoint_deterministic():
     torch = _torch()
     import paper_1908_06094_amd as mp
