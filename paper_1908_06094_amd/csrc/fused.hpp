@@ -66,20 +66,22 @@ struct DefaultLanes {
 };
 
 // Tile shape: a tile row is L lanes wide (a wave holds 64 / L rows) and the
-// workgroup's 768 threads hold `rows` rows.  The single-problem passes use
-// the default width of their type; the batched passes are also compiled for
-// the other widths, among which the autotuner picks.
-template <class T, int L = DefaultLanes<T>::value>
+// workgroup's N threads (768 unless stated) hold `rows` rows.  The
+// single-problem passes use the default width of their type; the batched
+// passes are also compiled for the other widths, among which the autotuner
+// picks.
+template <class T, int L = DefaultLanes<T>::value, int N = kThreads>
 struct Tile {
+    static constexpr int threads = N;
     static constexpr int lanes = L;
     static constexpr int shift = lanes == 64 ? 6 : (lanes == 32 ? 5 : 4);
-    static constexpr int rows = kThreads / lanes;
+    static constexpr int rows = N / lanes;
     static constexpr int tile_x = lanes - 2 * kHalo;   // interior columns
     static constexpr int tile_y = rows - 2 * kHalo;    // interior rows
     // workgroups per CU: the FP32 tile's LDS (57 KB) and registers (<= 80)
     // let two share a CU (6 waves per SIMD); the FP64 tile needs 114 KB
     static constexpr int wgs_per_cu = sizeof(T) == 4 ? 2 : 1;
-    static constexpr int waves_per_simd = wgs_per_cu * kThreads / 256;
+    static constexpr int waves_per_simd = wgs_per_cu * N / 256;
     // velocities handed between passes in the tile layout (FP32: its 112-byte
     // tile rows make the (nz, ny, nx) stores mostly partial cache lines; in
     // FP64 the 480-byte rows are not, and the tile layout measured slower).
@@ -98,7 +100,18 @@ struct Tile {
     static constexpr int donor_halo_x = sizeof(T) == 8 ? 3 : 2;
     static constexpr int donor_tile_x = lanes - 2 * donor_halo_x;
     static constexpr int donor_wgs_per_cu = 1;
-    static constexpr int donor_waves_per_simd = donor_wgs_per_cu * kThreads / 256;
+    static constexpr int donor_waves_per_simd = donor_wgs_per_cu * N / 256;
+};
+
+// Threads of the single-problem pass kernels: the FP32 donor-fused pass runs
+// 1024 (a 32 x 32 tile, 28 x 28 interior, 4 waves per SIMD in its 128
+// registers) where the others run 768; it hands its velocities over in the
+// layout of the plain pass's 28 x 20 interior.
+template <class T, bool DONOR>
+struct PassThreads {
+    static constexpr int value = DONOR && sizeof(T) == 4 ? 1024 : kThreads;
+    using TL = Tile<T, DefaultLanes<T>::value, value>;
+    static constexpr int waves_per_simd = DONOR ? TL::donor_waves_per_simd : TL::waves_per_simd;
 };
 
 // ---------------------------------------------------------------------------
@@ -280,9 +293,9 @@ __device__ __forceinline__ int map_index(int x, int n, int closed)
 // Is the face x+1/2 (virtual x) a closed wall or beyond one?
 __device__ __forceinline__ bool wall_face(int x, int n, int closed) { return closed && (x < 0 || x >= n - 1); }
 
-template <class T, int L = DefaultLanes<T>::value>
+template <class T, int L = DefaultLanes<T>::value, int N = kThreads>
 struct Slots {
-    static constexpr int kRows = Tile<T, L>::rows, kLanes = L;
+    static constexpr int kRows = Tile<T, L, N>::rows, kLanes = L, kThreads = N;
     // y-exchange planes, one value per (row, lane); phi, px and vpx keep the
     // last two planes (slot = plane parity) so that plane k's neighbours are
     // read one march step after they were published
@@ -298,10 +311,10 @@ struct Slots {
 // slots: psi^n and Cy of the current plane and of the next (rings by plane
 // parity), published one march step ahead of their use, from which each row
 // forms the donor-cell fluxes through its upper and its lower y face.
-template <class T, int L = DefaultLanes<T>::value>
-struct SlotsDonor : Slots<T, L> {
-    T psd[2][Tile<T, L>::rows][L];
-    T cyd[2][Tile<T, L>::rows][L];
+template <class T, int L = DefaultLanes<T>::value, int N = kThreads>
+struct SlotsDonor : Slots<T, L, N> {
+    T psd[2][Tile<T, L, N>::rows][L];
+    T cyd[2][Tile<T, L, N>::rows][L];
 };
 
 // One column's values of one plane: the loaded fields and what is derived
@@ -345,9 +358,10 @@ template <class T, bool LIMIT, bool WRITE_VEL, int ROLE, bool REC, bool DONOR, c
 __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, SL& S, const int tile,
                                           const int kb, const int ke)
 {
-    using TL = Tile<T, SL::kLanes>;
+    using TL = Tile<T, SL::kLanes, SL::kThreads>;
     constexpr int kLanes = TL::lanes, kRows = TL::rows;
     constexpr int kTileY = TL::tile_y;
+    constexpr int kLayY = Tile<T, SL::kLanes>::tile_y;   // the tile layout's block height (the plain pass's)
     // x halo and interior width of this kernel (the donor-fused FP64 pass
     // widens its x halo); the tile layout of handed-over velocities keeps the
     // plain pass's interior
@@ -375,12 +389,12 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
         const bool writer = lane >= kHX && lane < kLanes - kHX && row >= kHalo && row < kRows - kHalo &&
                             gi < geo.nx && gj < geo.ny;
         // this lane's cell in the tile layout of the velocities (blocks of
-        // the plain pass's kLayX x kTileY interior)
+        // the plain pass's kLayX x kLayY interior)
         const int lay_tiles_x = (geo.nx + kLayX - 1) / kLayX;
-        const int lay_tiles_y = (geo.ny + kTileY - 1) / kTileY;
-        const int ttx = ci / kLayX, tty = cj / kTileY;
-        const unsigned tcol = (unsigned)((tty * lay_tiles_x + ttx) * (kLayX * kTileY) +
-                                         (cj - tty * kTileY) * kLayX + (ci - ttx * kLayX));
+        const int lay_tiles_y = (geo.ny + kLayY - 1) / kLayY;
+        const int ttx = ci / kLayX, tty = cj / kLayY;
+        const unsigned tcol = (unsigned)((tty * lay_tiles_x + ttx) * (kLayX * kLayY) +
+                                         (cj - tty * kLayY) * kLayX + (ci - ttx * kLayX));
         const long long tplane = tiled_plane<T>(lay_tiles_x, lay_tiles_y);
 
         // plane loader: cell quantities through the halo rule.  Every load is
@@ -802,8 +816,8 @@ __device__ __forceinline__ void pass_segment(const Geo& geo, const PassArgs<T>& 
 }
 
 // Slots of a pass kernel (the donor-fused pass needs three more planes).
-template <class T, bool DONOR, int L = DefaultLanes<T>::value>
-using PassSlots = typename std::conditional<DONOR, SlotsDonor<T, L>, Slots<T, L>>::type;
+template <class T, bool DONOR, int L = DefaultLanes<T>::value, int N = kThreads>
+using PassSlots = typename std::conditional<DONOR, SlotsDonor<T, L, N>, Slots<T, L, N>>::type;
 
 // Logical workgroup id: the dispatcher deals workgroups round-robin over the
 // 8 XCDs; consecutive logical ids (hence neighbouring work) share one XCD.
@@ -818,10 +832,10 @@ __device__ __forceinline__ int xcd_grouped_id()
 // workgroup, so every workgroup marches the same number of planes (a range
 // may span a tile boundary).
 template <class T, bool LIMIT, bool WRITE_VEL, bool REC = false, bool DONOR = false>
-__global__ void __launch_bounds__(kThreads, DONOR ? Tile<T>::donor_waves_per_simd : Tile<T>::waves_per_simd)
+__global__ void __launch_bounds__((PassThreads<T, DONOR>::value), (PassThreads<T, DONOR>::waves_per_simd))
     k_pass(Geo geo, PassArgs<T> a)
 {
-    __shared__ PassSlots<T, DONOR> S;
+    __shared__ PassSlots<T, DONOR, DefaultLanes<T>::value, PassThreads<T, DONOR>::value> S;
     const int nwg = gridDim.x;
     const int wg = xcd_grouped_id();
     const long long total = (long long)a.tiles_x * a.tiles_y * geo.nz;

@@ -375,7 +375,8 @@ int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hi
     Timed tm(DONOR ? MPDATA_KERNEL_PASS_DONOR : MPDATA_KERNEL_PASS, st);
     using TL = mpdata::fused::Tile<T>;
     const int grid = pass_grid(total) * (DONOR ? TL::donor_wgs_per_cu : TL::wgs_per_cu);
-    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC, DONOR><<<grid, mpdata::fused::kThreads, 0, st>>>(g, a);
+    constexpr int threads = mpdata::fused::PassThreads<T, DONOR>::value;
+    mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC, DONOR><<<grid, threads, 0, st>>>(g, a);
     return launch_status(DONOR ? "fused donor-cell and first corrective pass" : "fused corrective pass");
 }
 
@@ -440,8 +441,12 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
         T* nxt = last ? psout : (phi == b.phi[0] ? b.phi[1] : b.phi[0]);
         const bool donor = fold && m == 2;
         a.phi = donor ? nullptr : phi;   // the donor-fused pass forms psi^(1) itself
-        a.tiles_x = (p->nx + (donor ? mpdata::fused::Tile<T>::donor_tile_x : mpdata::fused::Tile<T>::tile_x) - 1) /
-                    (donor ? mpdata::fused::Tile<T>::donor_tile_x : mpdata::fused::Tile<T>::tile_x);
+        using DT = mpdata::fused::Tile<T, mpdata::fused::DefaultLanes<T>::value,
+                                       mpdata::fused::PassThreads<T, true>::value>;   // the donor-fused pass's tile
+        a.tiles_x = (p->nx + (donor ? DT::donor_tile_x : mpdata::fused::Tile<T>::tile_x) - 1) /
+                    (donor ? DT::donor_tile_x : mpdata::fused::Tile<T>::tile_x);
+        a.tiles_y = (p->ny + (donor ? DT::tile_y : mpdata::fused::Tile<T>::tile_y) - 1) /
+                    (donor ? DT::tile_y : mpdata::fused::Tile<T>::tile_y);
         a.out = nxt;
         a.ul = b.vel[vsel][0];
         a.vl = b.vel[vsel][1];
