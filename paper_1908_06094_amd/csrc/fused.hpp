@@ -405,7 +405,9 @@ __device__ __forceinline__ void pass_rows(const Geo& geo, const PassArgs<T>& a, 
         // DONOR: the neighbours beyond the row's ends and the tile's outer rows
         const bool x_lo = lane == 0, x_hi = lane == kLanes - 1;
         const bool y_lo = row == 0, y_hi = row == kRows - 1;
-        constexpr bool kOuterRows = ROLE == 2 || sizeof(T) == 4;   // waves that may hold rows 0 and R-1
+        // waves that may hold rows 0 and R-1: FP32 runs every wave in role 0,
+        // and a wave of several rows takes the role of its innermost one
+        constexpr bool kOuterRows = ROLE == 2 || sizeof(T) == 4 || kLanes < 64;
         const unsigned col_xe = (unsigned)(cj * (int)geo.sy + map_index(x_lo ? gi - 1 : gi + 1, geo.nx, geo.closed_x));
         const unsigned col_ye = (unsigned)(map_index(y_lo ? gj - 1 : gj + 1, geo.ny, geo.closed_y) * (int)geo.sy + ci);
         const bool xwall_l = wall_face(gi - 1, geo.nx, geo.closed_x);   // the face left of the cell
