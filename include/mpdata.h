@@ -138,7 +138,10 @@ int mpdata_run(const mpdata_problem* p, int32_t nsteps, void* psi,
  * took ([c]+ differentiates to [c > 0], 1/2 at c = 0, |c| to sign(c) with sign(0) = 0,
  * min(1, min(a, b)) to its first minimal entry, the limiter bounds to their
  * first extremal entry).  psiT_out (nullable) receives psi_T.  No atomics:
- * the result is bitwise reproducible.  ws: at least the MPDATA_OP_ADJOINT
+ * the result is bitwise reproducible.  With the environment variable
+ * MPDATA_ADJOINT=march the antidiffusive-velocity adjoint of a limited pass
+ * runs as one k-marching kernel instead of two gather kernels (the same
+ * result bit for bit; slower on MI355X, kept for comparison).  ws: at least the MPDATA_OP_ADJOINT
  * size for the same nsteps and checkpoint_every.  No output (dJ_dpsi0,
  * dJ_dc*, psiT_out) may alias an input, another output or the workspace
  * (MPDATA_EINVAL).  The MPDATA iterations and
