@@ -357,11 +357,14 @@ int cu_count()
 
 // Persistent grid of the fused passes: one workgroup per CU (their LDS
 // allows no more), a multiple of 8 (the XCD count the work split groups by),
-// and no more workgroups than leave each at least ~12 output planes.
+// and no more workgroups than leave each at least ~12 output planes, except
+// that a small problem spreads over up to 64 workgroups (a 64 x 64 plane has
+// 16 tile planes: one workgroup each instead of 8 with two tiles in turn).
 int pass_grid(long long total_planes)
 {
     long long n = cu_count();
     long long cap = total_planes / 12;
+    if (cap < 64) cap = total_planes < 64 ? total_planes : 64;
     if (n > cap) n = cap;
     n &= ~7LL;
     return n < 8 ? 8 : (int)n;
