@@ -132,7 +132,12 @@ __global__ void __launch_bounds__(256) k_ustep_wave(UArgs<T> a)
 // level blocks; the offsets are 32-bit (the host uses the one-wave kernel
 // for meshes whose (node or edge) x level count reaches 2^31).  Edges are
 // summed in the node-to-edge table's order, as in the one-wave mapping.
-constexpr int kLevelLanes = 16;
+// Lanes per node (a build option; on O128 x 80 levels 16 measured 145 us,
+// 32 lanes 180 us, 8 lanes 170 us).
+#ifndef MPDATA_USTEP_LANES
+#define MPDATA_USTEP_LANES 16
+#endif
+constexpr int kLevelLanes = MPDATA_USTEP_LANES;
 constexpr int kNodesPerWave = 64 / kLevelLanes;
 
 template <class T>
