@@ -328,15 +328,16 @@ def time_unstructured(mp, torch, dev, steps=20, cpu=True):
     grid of 70 144 nodes (O128: 209 864 edges) x 80 levels, FP64 (solid-body
     winds through the dual faces, a zero vertical wind read all the same,
     unit density, a cosine bell plus noise), `steps` steps; and the same
-    mesh with its nodes and edges numbered at random, against the row-by-row
-    numbering (the kernel and the arithmetic are the same; only the memory
-    locality of the gathers differs)."""
+    mesh with its nodes and edges numbered at random and along a Hilbert
+    curve, against the row-by-row numbering (the kernel and the arithmetic
+    are the same; only the memory locality of the gathers differs)."""
     from workloads import octahedral as octa
 
     u = octa.octahedral_workload(128, 80)
     m = u.mesh
     wall, avg_s = _urun_timed(mp, torch, dev, u, steps)
     _, avg_r = _urun_timed(mp, torch, dev, octa.renumbered_workload(u), steps)
+    _, avg_h = _urun_timed(mp, torch, dev, octa.renumbered_workload(u, numbering="hilbert"), steps)
     # algorithmic traffic per step: read psi, w, rho and write psi per node
     # and level, read vn per edge and level (the edge fluxes and the vertical
     # fluxes stay on chip)
@@ -348,7 +349,9 @@ def time_unstructured(mp, torch, dev, steps=20, cpu=True):
            "hbm_frac": round(nbytes / avg_s / 1e9 / HBM_PEAK_GBS, 4),
            "table2_accesses_per_plane_fused": 5 * m.n_nodes,
            "numbering": {"row_by_row_kernel_us": round(avg_s * 1e6, 2), "random_kernel_us": round(avg_r * 1e6, 2),
-                         "random_over_row_by_row": round(avg_r / avg_s, 3)}}
+                         "hilbert_kernel_us": round(avg_h * 1e6, 2),
+                         "random_over_row_by_row": round(avg_r / avg_s, 3),
+                         "hilbert_over_row_by_row": round(avg_h / avg_s, 3)}}
     if cpu:
         import oracle
 

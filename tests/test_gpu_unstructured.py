@@ -25,12 +25,12 @@ def _say(msg):
 @pytest.mark.parametrize("N,nz,pivbz,steps,with_w", [(3, 1, 0.0, 1, True), (4, 7, 0.0, 3, True),
                                                        (6, 80, 1.0, 2, True), (5, 13, 0.5, 4, False),
                                                        (8, 3, 0.0, 5, True)])
-@pytest.mark.parametrize("renumber", [False, True])
+@pytest.mark.parametrize("renumber", [None, "random", "hilbert"])
 @pytest.mark.parametrize("mapping", ["grouped", "wave"])
 def test_ustep_matches_oracle(N, nz, pivbz, steps, with_w, renumber, mapping, monkeypatch):
     """Both kernel mappings (four nodes per wave, and one wave per node),
-    on the row-by-row numbered mesh and on a random renumbering of it:
-    bitwise equal to the oracle on the same mesh."""
+    on the row-by-row numbered mesh and on a random and a Hilbert-curve
+    renumbering of it: bitwise equal to the oracle on the same mesh."""
     torch = _torch()
     import paper_1908_06094_amd as mp
 
@@ -41,7 +41,7 @@ def test_ustep_matches_oracle(N, nz, pivbz, steps, with_w, renumber, mapping, mo
     _say(f"[unstructured] O{N} nz={nz} pivbz={pivbz} steps={steps} w={with_w} renumbered={renumber} {mapping}")
     u = octa.random_uproblem(N, nz, seed=N * 100 + nz, pivbz=pivbz)
     if renumber:
-        u = octa.renumbered_workload(u, seed=N)
+        u = octa.renumbered_workload(u, seed=N, numbering=renumber)
     m = u.mesh
     w = u.w if with_w else np.zeros_like(u.w)
     want = oracle.urun(steps, m.edges, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, u.psi, u.vn, w,

@@ -123,6 +123,36 @@ def test_rejects_bad_connectivity():
         oracle.ustep(bad, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, f, np.zeros((m.n_edges, nz)), f, f)
 
 
+def test_hilbert_index_walks_the_grid():
+    """The Hilbert numbering's curve: on a 2^k x 2^k grid it visits every
+    point once, and consecutive points are grid neighbours (a wrong rotation
+    or reflection of a quadrant breaks the second property)."""
+    for k in (1, 2, 3, 4, 6):
+        n = 1 << k
+        x, y = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        d = octa.hilbert_index(x.ravel(), y.ravel(), k)
+        assert np.array_equal(np.sort(d), np.arange(n * n))
+        order = np.argsort(d)
+        steps = np.abs(np.diff(x.ravel()[order])) + np.abs(np.diff(y.ravel()[order]))
+        assert np.all(steps == 1), k
+
+
+@pytest.mark.parametrize("numbering", ["random", "hilbert"])
+def test_renumbered_mesh_gives_the_same_step_any_numbering(numbering):
+    """The same octahedral mesh numbered at random or along a Hilbert curve:
+    the step gives every node the same value up to the order of its edge sum."""
+    u = octa.random_uproblem(6, 5, seed=3, pivbz=0.5)
+    r = octa.renumbered_workload(u, 11, numbering=numbering)
+    perms = octa.hilbert_order(u.mesh) if numbering == "hilbert" else None
+    _, (node_perm, edge_perm) = octa.renumbered(u.mesh, 11, perms)
+    assert sorted(node_perm) == list(range(u.mesh.n_nodes)) and sorted(edge_perm) == list(range(u.mesh.n_edges))
+    m, mr = u.mesh, r.mesh
+    a = oracle.ustep(m.edges, m.node_ptr, m.node_edges, m.node_sign, m.dual_volume, u.psi, u.vn, u.w, u.rho, u.pivbz)
+    b = oracle.ustep(mr.edges, mr.node_ptr, mr.node_edges, mr.node_sign, mr.dual_volume, r.psi, r.vn, r.w, r.rho,
+                     r.pivbz)
+    assert np.max(np.abs(b - a[node_perm])) <= 1e-15 * np.max(np.abs(a))
+
+
 def test_renumbered_mesh_gives_the_same_step():
     """The same octahedral mesh with nodes and edges numbered at random (the
     unstructured numbering the benchmark compares with the row-by-row one):

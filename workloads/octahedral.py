@@ -235,17 +235,59 @@ def random_uproblem(N: int, nz: int, seed: int, courant: float = 0.4, pivbz: flo
     return UWorkload(f"random-O{N}-{nz}", mesh, nz, psi, vn, w, rho, pivbz)
 
 
-def renumbered(mesh: OctaMesh, seed: int):
+def hilbert_index(x: np.ndarray, y: np.ndarray, order: int) -> np.ndarray:
+    """Position along the Hilbert curve of the 2^order x 2^order grid of each
+    integer point (x, y) (the curve's recursive definition: at each scale the
+    quadrant index, with the sub-square rotated or reflected so that the
+    curve's pieces join end to end)."""
+    x = np.asarray(x, dtype=np.int64).copy()
+    y = np.asarray(y, dtype=np.int64).copy()
+    d = np.zeros_like(x)
+    s = 1 << (order - 1)
+    while s > 0:
+        rx = (x & s) > 0
+        ry = (y & s) > 0
+        d += s * s * ((3 * rx) ^ ry)
+        # rotate the quadrant so that the curve inside it starts and ends where it must
+        flip = ~ry
+        swap_x = flip & rx
+        x = np.where(swap_x, s - 1 - x, x)
+        y = np.where(swap_x, s - 1 - y, y)
+        x, y = np.where(flip, y, x), np.where(flip, x, y)
+        s >>= 1
+    return d
+
+
+def hilbert_order(mesh: OctaMesh, order: int = 10):
+    """Node and edge orders along a Hilbert curve over (longitude, latitude)
+    mapped to a 2^order square: the paper's third numbering of its indexing
+    study, a space-filling curve.  Returns (node_perm, edge_perm) in the
+    convention of `renumbered`; edges follow the curve position of their
+    midpoint (the mean of their end nodes' curve coordinates)."""
+    n = 1 << order
+    gx = np.minimum((mesh.lon / (2 * np.pi) * n).astype(np.int64), n - 1)
+    gy = np.minimum(((mesh.lat + np.pi / 2) / np.pi * n).astype(np.int64), n - 1)
+    node_perm = np.argsort(hilbert_index(gx, gy, order), kind="stable")
+    a, b = mesh.edges[:, 0].astype(np.int64), mesh.edges[:, 1].astype(np.int64)
+    edge_perm = np.argsort(hilbert_index((gx[a] + gx[b]) // 2, (gy[a] + gy[b]) // 2, order), kind="stable")
+    return node_perm, edge_perm
+
+
+def renumbered(mesh: OctaMesh, seed: int, perms=None):
     """The same mesh with its nodes and edges numbered in a random order (an
-    unstructured numbering, against the row-by-row one of `build`).  Returns
-    the new mesh and (node_perm, edge_perm): new node i is old node
-    node_perm[i], new edge e is old edge edge_perm[e].  Each edge keeps its
-    orientation (ip1 -> ip2), so fluxes and their signs carry over; a node's
-    edges are listed in ascending new edge number."""
-    rng = np.random.default_rng(seed)
+    unstructured numbering, against the row-by-row one of `build`), or in the
+    given order perms = (node_perm, edge_perm).  Returns the new mesh and
+    (node_perm, edge_perm): new node i is old node node_perm[i], new edge e is
+    old edge edge_perm[e].  Each edge keeps its orientation (ip1 -> ip2), so
+    fluxes and their signs carry over; a node's edges are listed in ascending
+    new edge number."""
     nn, ne = mesh.n_nodes, mesh.n_edges
-    node_perm = rng.permutation(nn)
-    edge_perm = rng.permutation(ne)
+    if perms is None:
+        rng = np.random.default_rng(seed)
+        node_perm = rng.permutation(nn)
+        edge_perm = rng.permutation(ne)
+    else:
+        node_perm, edge_perm = (np.asarray(p, dtype=np.int64) for p in perms)
     new_of_node = np.empty(nn, dtype=np.int64)
     new_of_node[node_perm] = np.arange(nn)
     edges = new_of_node[mesh.edges[edge_perm].astype(np.int64)].astype(np.int32)
@@ -263,10 +305,12 @@ def renumbered(mesh: OctaMesh, seed: int):
     return out, (node_perm, edge_perm)
 
 
-def renumbered_workload(u: UWorkload, seed: int = 7) -> UWorkload:
-    """Workload u on its mesh with nodes and edges numbered at random (fields
-    permuted to match)."""
-    mesh, (np_, ep) = renumbered(u.mesh, seed)
-    return UWorkload(u.name + "-renumbered", mesh, u.nz, np.ascontiguousarray(u.psi[np_]),
+def renumbered_workload(u: UWorkload, seed: int = 7, numbering: str = "random") -> UWorkload:
+    """Workload u on its mesh with nodes and edges numbered at random
+    (numbering "random") or along a Hilbert curve ("hilbert"), fields
+    permuted to match."""
+    perms = hilbert_order(u.mesh) if numbering == "hilbert" else None
+    mesh, (np_, ep) = renumbered(u.mesh, seed, perms)
+    return UWorkload(u.name + "-" + numbering, mesh, u.nz, np.ascontiguousarray(u.psi[np_]),
                      np.ascontiguousarray(u.vn[ep]), np.ascontiguousarray(u.w[np_]),
                      np.ascontiguousarray(u.rho[np_]), u.pivbz)
