@@ -168,11 +168,14 @@ int mpdata_adjoint(const mpdata_problem* p, int32_t nsteps, int32_t checkpoint_e
  *                       on this batch (FP32: tile rows of 32, 64 or 16 lanes,
  *                       i.e. 28 x 20, 60 x 8 or 12 x 44 interior cells per
  *                       768-thread tile, times one or two workgroups per CU,
- *                       times the donor-cell pass inside the first
- *                       corrective pass or as its own kernel: variants
- *                       0 .. 5 = (32, 1), (32, 2), (64, 1), (64, 2), (16, 1),
- *                       (16, 2) folded and 6 .. 11 the same split; FP64:
- *                       0 folded, 1 split, 64 lanes, one workgroup); the
+ *                       or 1024-thread tiles (28 x 28, 60 x 12, 12 x 60
+ *                       interior cells) one per CU, times the donor-cell
+ *                       pass inside the first corrective pass or as its own
+ *                       kernel: variants 0 .. 5 = (32, 1), (32, 2), (64, 1),
+ *                       (64, 2), (16, 1), (16, 2) folded and 6 .. 11 the same
+ *                       split, 12 .. 14 = 1024 threads with 32, 64, 16 lanes
+ *                       folded and 15 .. 17 the same split; FP64: 0 folded,
+ *                       1 split, 64 lanes, one workgroup); the
  *                       choice is kept per batch shape and appended to the
  *                       file named by the environment variable
  *                       MPDATA_TUNE_CACHE as a line "<batch shape>\t<variant>"

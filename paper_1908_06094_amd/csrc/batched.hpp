@@ -130,11 +130,11 @@ struct Tables {
 
 // Tables for the tile of row width LANES.  fold: the donor-cell pass runs
 // inside the first corrective pass (its tile may be narrower, FP64).
-template <class T, int LANES>
+template <class T, int LANES, int N = mpdata::fused::kThreads>
 Tables<T> build_tables(const mpdata_problem* c, int n, const mpdata_batch_item* items, const Layout& L, char* ws,
                        bool fold)
 {
-    using TL = mpdata::fused::Tile<T, LANES>;
+    using TL = mpdata::fused::Tile<T, LANES, N>;
     Tables<T> tb;
     const int M = c->iters;
     const double eps = c->eps > 0.0 ? c->eps : 1e-15;

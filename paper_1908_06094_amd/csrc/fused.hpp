@@ -870,13 +870,16 @@ struct BatchEntry {
     int vel_per_tracer;      // previous velocities are per tracer (passes >= 3)
 };
 
-// WAVES_PER_SIMD: 3 = one workgroup per CU (up to 168 VGPRs per wave);
-// 6 = two workgroups per CU (the FP32 kernel's LDS allows it; VGPRs <= 80).
-template <class T, bool LIMIT, bool WRITE_VEL, int WAVES_PER_SIMD, bool DONOR = false, int L = DefaultLanes<T>::value>
-__global__ void __launch_bounds__(kThreads, WAVES_PER_SIMD) k_pass_batched(const BatchEntry<T>* __restrict__ tab,
-                                                                           int n_entries, long long total)
+// N threads per workgroup (768: 12 waves; 1024: 16 waves, the tile
+// 1024 / L rows tall).  WAVES_PER_SIMD: 3 = one 768-thread workgroup per CU
+// (up to 168 VGPRs per wave); 6 = two (the FP32 kernel's LDS allows it;
+// VGPRs <= 80); 4 = one 1024-thread workgroup (VGPRs <= 128).
+template <class T, bool LIMIT, bool WRITE_VEL, int WAVES_PER_SIMD, bool DONOR = false, int L = DefaultLanes<T>::value,
+          int N = kThreads>
+__global__ void __launch_bounds__(N, WAVES_PER_SIMD) k_pass_batched(const BatchEntry<T>* __restrict__ tab,
+                                                                    int n_entries, long long total)
 {
-    __shared__ PassSlots<T, DONOR, L> S;
+    __shared__ PassSlots<T, DONOR, L, N> S;
     const int nwg = gridDim.x;
     const int wg = xcd_grouped_id();
     const long long span = (total + nwg - 1) / nwg;

@@ -912,12 +912,16 @@ hipStream_t g_capture_stream[64] = {nullptr};
 struct BatchVariant {
     int lanes, waves_per_simd;
     bool fold;
+    int threads;   // per workgroup: 768 (12 waves) or 1024 (16 waves, 1024 / lanes rows)
 };
-constexpr BatchVariant kVariantsF32[] = {{32, 3, true},  {32, 6, true},  {64, 3, true},  {64, 6, true},
-                                         {16, 3, true},  {16, 6, true},  {32, 3, false}, {32, 6, false},
-                                         {64, 3, false}, {64, 6, false}, {16, 3, false}, {16, 6, false}};
-constexpr BatchVariant kVariantsF64[] = {{64, 3, true}, {64, 3, false}};
-int variant_count(int dtype) { return dtype == MPDATA_F32 ? 12 : 2; }
+constexpr BatchVariant kVariantsF32[] = {
+    {32, 3, true, 768},   {32, 6, true, 768},   {64, 3, true, 768},   {64, 6, true, 768},
+    {16, 3, true, 768},   {16, 6, true, 768},   {32, 3, false, 768},  {32, 6, false, 768},
+    {64, 3, false, 768},  {64, 6, false, 768},  {16, 3, false, 768},  {16, 6, false, 768},
+    {32, 4, true, 1024},  {64, 4, true, 1024},  {16, 4, true, 1024},
+    {32, 4, false, 1024}, {64, 4, false, 1024}, {16, 4, false, 1024}};
+constexpr BatchVariant kVariantsF64[] = {{64, 3, true, 768}, {64, 3, false, 768}};
+int variant_count(int dtype) { return dtype == MPDATA_F32 ? 18 : 2; }
 BatchVariant variant_of(int dtype, int v) { return dtype == MPDATA_F32 ? kVariantsF32[v] : kVariantsF64[v]; }
 
 std::string shape_key(const mpdata_problem* c, int n, const mpdata_batch_item* items)
@@ -975,10 +979,10 @@ struct BatchDev {
     const mpdata::stages::DonorEntry<T>* copyback;
 };
 
-// One step's launches for the variant of row width LANES and WPS waves per
-// SIMD: the donor-cell pass unless the first corrective pass carries it,
-// then the corrective passes.
-template <class T, int LANES, int WPS>
+// One step's launches for the variant of row width LANES, WPS waves per SIMD
+// and N threads per workgroup: the donor-cell pass unless the first
+// corrective pass carries it, then the corrective passes.
+template <class T, int LANES, int WPS, int N = mpdata::fused::kThreads>
 int enqueue_batched_step_v(const mpdata_problem* c, int n, const batch::Tables<T>& tb, const BatchDev<T>& dv, int par,
                            hipStream_t st)
 {
@@ -999,7 +1003,7 @@ int enqueue_batched_step_v(const mpdata_problem* c, int n, const batch::Tables<T
         const int grid = (int)(WPS == 6 ? g1 * 2 : g1);
         Timed tm(donor ? MPDATA_KERNEL_PASS_DONOR : MPDATA_KERNEL_PASS, st);
 #define MPDATA_LAUNCH(LIM, WV, DN) \
-    mpdata::fused::k_pass_batched<T, LIM, WV, WPS, DN, LANES><<<grid, mpdata::fused::kThreads, 0, st>>>(tab, n, total)
+    mpdata::fused::k_pass_batched<T, LIM, WV, WPS, DN, LANES, N><<<grid, N, 0, st>>>(tab, n, total)
         if (donor) {
             if (c->limiter) { if (last) MPDATA_LAUNCH(true, false, true); else MPDATA_LAUNCH(true, true, true); }
             else { if (last) MPDATA_LAUNCH(false, false, true); else MPDATA_LAUNCH(false, true, true); }
@@ -1022,7 +1026,15 @@ int enqueue_batched_step(const mpdata_problem* c, int n, const batch::Tables<T>&
                                            : fail(MPDATA_EINVAL, "batched kernel variant %d does not exist in FP64",
                                                   variant);
     } else {
-        // the fold is the tables' (variants v and v + 6 share their kernels)
+        // the fold is the tables' (variants v and v + 6 of the first twelve,
+        // and v and v + 3 of the last six, share their kernels)
+        if (variant >= 12 && variant < 18) {
+            switch ((variant - 12) % 3) {
+            case 0: return enqueue_batched_step_v<T, 32, 4, 1024>(c, n, tb, dv, par, st);
+            case 1: return enqueue_batched_step_v<T, 64, 4, 1024>(c, n, tb, dv, par, st);
+            default: return enqueue_batched_step_v<T, 16, 4, 1024>(c, n, tb, dv, par, st);
+            }
+        }
         switch (variant % 6) {
         case 0: return enqueue_batched_step_v<T, 32, 3>(c, n, tb, dv, par, st);
         case 1: return enqueue_batched_step_v<T, 32, 6>(c, n, tb, dv, par, st);
@@ -1046,6 +1058,11 @@ batch::Tables<T> tables_for(const mpdata_problem* c, int n, const mpdata_batch_i
         return batch::build_tables<T, 64>(c, n, items, L, ws, fold);
     } else {
         const int lanes = kVariantsF32[variant].lanes;
+        if (kVariantsF32[variant].threads == 1024) {
+            if (lanes == 16) return batch::build_tables<T, 16, 1024>(c, n, items, L, ws, fold);
+            if (lanes == 32) return batch::build_tables<T, 32, 1024>(c, n, items, L, ws, fold);
+            return batch::build_tables<T, 64, 1024>(c, n, items, L, ws, fold);
+        }
         if (lanes == 16) return batch::build_tables<T, 16>(c, n, items, L, ws, fold);
         if (lanes == 32) return batch::build_tables<T, 32>(c, n, items, L, ws, fold);
         return batch::build_tables<T, 64>(c, n, items, L, ws, fold);

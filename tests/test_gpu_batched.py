@@ -140,11 +140,14 @@ def test_graph_replays_match_eager():
             assert torch.equal(a["psi"], b["psi"]), rep
 
 
-# The batched kernel variants (FP32): tile row width x workgroups per CU x
-# donor-cell pass folded into the first corrective pass or separate.
-VARIANTS_F32 = [(32, 1, "fold"), (32, 2, "fold"), (64, 1, "fold"), (64, 2, "fold"), (16, 1, "fold"),
-                (16, 2, "fold"), (32, 1, "split"), (32, 2, "split"), (64, 1, "split"), (64, 2, "split"),
-                (16, 1, "split"), (16, 2, "split")]
+# The batched kernel variants (FP32): tile row width x threads per workgroup
+# (the tile's rows: threads / row width) x workgroups per CU x donor-cell pass
+# folded into the first corrective pass or separate.
+VARIANTS_F32 = [(32, 768, 1, "fold"), (32, 768, 2, "fold"), (64, 768, 1, "fold"), (64, 768, 2, "fold"),
+                (16, 768, 1, "fold"), (16, 768, 2, "fold"), (32, 768, 1, "split"), (32, 768, 2, "split"),
+                (64, 768, 1, "split"), (64, 768, 2, "split"), (16, 768, 1, "split"), (16, 768, 2, "split"),
+                (32, 1024, 1, "fold"), (64, 1024, 1, "fold"), (16, 1024, 1, "fold"),
+                (32, 1024, 1, "split"), (64, 1024, 1, "split"), (16, 1024, 1, "split")]
 
 
 @pytest.mark.parametrize("variant", range(len(VARIANTS_F32)))
@@ -156,8 +159,9 @@ def test_every_f32_variant_matches_oracle_and_single_path(variant, iters, monkey
     torch = _torch()
     import paper_1908_06094_amd as mp
 
-    lanes, wgs, fold = VARIANTS_F32[variant]
-    _say(f"[batched] variant {variant} ({lanes} lanes, {wgs} workgroup(s) per CU, {fold}) iters={iters}")
+    lanes, threads, wgs, fold = VARIANTS_F32[variant]
+    _say(f"[batched] variant {variant} ({lanes} lanes, {threads} threads, {wgs} workgroup(s) per CU, {fold}) "
+         f"iters={iters}")
     monkeypatch.setenv("MPDATA_BATCH_VARIANT", str(variant))
     probs, host = _batch("f32", seed=40 + variant)
     single = []
