@@ -376,7 +376,7 @@ int launch_pass(const mpdata_problem* p, const mpdata::fused::PassArgs<T>& a, hi
     mpdata::Geo g = geo_of(p);
     const long long total = (long long)a.tiles_x * a.tiles_y * p->nz;
     Timed tm(DONOR ? MPDATA_KERNEL_PASS_DONOR : MPDATA_KERNEL_PASS, st);
-    using TL = mpdata::fused::Tile<T>;
+    using TL = typename mpdata::fused::PassThreads<T, DONOR>::TL;
     const int grid = pass_grid(total) * (DONOR ? TL::donor_wgs_per_cu : TL::wgs_per_cu);
     constexpr int threads = mpdata::fused::PassThreads<T, DONOR>::value;
     mpdata::fused::k_pass<T, LIMIT, WRITE_VEL, REC, DONOR><<<grid, threads, 0, st>>>(g, a);
@@ -448,8 +448,8 @@ int step_fused(const mpdata_problem* p, const T* psin, T* psout, const T* cx, co
                                        mpdata::fused::PassThreads<T, true>::value>;   // the donor-fused pass's tile
         a.tiles_x = (p->nx + (donor ? DT::donor_tile_x : mpdata::fused::Tile<T>::tile_x) - 1) /
                     (donor ? DT::donor_tile_x : mpdata::fused::Tile<T>::tile_x);
-        a.tiles_y = (p->ny + (donor ? DT::tile_y : mpdata::fused::Tile<T>::tile_y) - 1) /
-                    (donor ? DT::tile_y : mpdata::fused::Tile<T>::tile_y);
+        using PT = typename mpdata::fused::PassThreads<T, false>::TL;   // the plain pass's tile
+        a.tiles_y = (p->ny + (donor ? DT::tile_y : PT::tile_y) - 1) / (donor ? DT::tile_y : PT::tile_y);
         a.out = nxt;
         a.ul = b.vel[vsel][0];
         a.vl = b.vel[vsel][1];
