@@ -616,12 +616,15 @@ int step_adjoint_fwd(const mpdata_problem* p, const double* psin, double* psout,
     a.psin = psin;
     a.g = gm;
     a.eps = p->eps > 0.0 ? p->eps : 1e-15;
-    a.tiles_y = (p->ny + F::Tile<double>::tile_y - 1) / F::Tile<double>::tile_y;
     a.vel_tiled = 0;
+    using DT = F::PassThreads<double, true>::TL;    // the donor-fused pass's tile
+    using PT = F::PassThreads<double, false>::TL;   // the plain pass's
     for (int m = 2; m <= M; ++m) {
         const bool donor = m == 2, last = m == M;
-        const int tile_x = donor ? F::Tile<double>::donor_tile_x : F::Tile<double>::tile_x;
+        const int tile_x = donor ? DT::donor_tile_x : PT::tile_x;
+        const int tile_y = donor ? DT::tile_y : PT::tile_y;
         a.tiles_x = (p->nx + tile_x - 1) / tile_x;
+        a.tiles_y = (p->ny + tile_y - 1) / tile_y;
         a.phi = donor ? nullptr : R.phis[m - 1];
         a.rphi = record && donor ? R.phis[1] : nullptr;
         a.out = last ? psout : R.phis[m];
