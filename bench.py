@@ -272,9 +272,30 @@ def time_batched(mp, torch, dev, steps=20, reps=3):
     _, _, nb = mp.batch_problem(probs, iters=2)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream(dev)
+    # the tuner appends its choice to the file MPDATA_TUNE_CACHE names
+    import tempfile
+
+    old_cache = os.environ.get("MPDATA_TUNE_CACHE")
+    cache = tempfile.NamedTemporaryFile(prefix="mpdata_tune_", suffix=".txt", delete=False)
+    cache.close()
+    os.environ["MPDATA_TUNE_CACHE"] = cache.name
     with torch.cuda.stream(stream):
         mp.run_batched(probs, steps, iters=2, graph=True, tune=True, workspace=ws, stream=stream)  # tune + capture
         stream.synchronize()
+    if old_cache is None:
+        del os.environ["MPDATA_TUNE_CACHE"]
+    else:
+        os.environ["MPDATA_TUNE_CACHE"] = old_cache
+    with open(cache.name) as f:
+        lines = [ln.rstrip("\n").split("\t") for ln in f if ln.strip()]
+    os.unlink(cache.name)
+    tuned = None
+    if lines and lines[-1][-1].isdigit():
+        v = int(lines[-1][-1])
+        lanes, threads, wgs, donor = mp.BATCH_VARIANTS_F32[v]
+        tuned = {"index": v, "row_lanes": lanes, "threads": threads, "workgroups_per_cu": wgs,
+                 "donor_cell_pass": donor}
+    with torch.cuda.stream(stream):
         times = []
         for _ in range(reps):
             for p, s0 in zip(probs, start):
@@ -289,7 +310,7 @@ def time_batched(mp, torch, dev, steps=20, reps=3):
     return {"workload": f"64 lat-lon problems (nx 64-512, ny 32-256, nz 20-80), 1-8 tracers, FP32, 2 passes, "
                         f"limiter, {steps} steps, HIP graph",
             "tracer_cells": tracer_cells, "value": round(tracer_cells * steps / t, 1),
-            "unit": "tracer-cell updates/s", "ms_per_step": round(t * 1e3 / steps, 4)}
+            "unit": "tracer-cell updates/s", "ms_per_step": round(t * 1e3 / steps, 4), "tuned_variant": tuned}
 
 
 def cpu_model() -> str:

@@ -27,6 +27,8 @@ from ._lib import (  # noqa: F401
     MPDATA_PERIODIC,
     MPDATA_BATCH_GRAPH,
     MPDATA_BATCH_TUNE,
+    BATCH_VARIANTS_F32,
+    BATCH_VARIANTS_F64,
     BatchItem,
     DeviceMesh,
     UMesh,

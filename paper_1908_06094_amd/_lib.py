@@ -275,6 +275,16 @@ def mpdata_function():
 
 MPDATA_BATCH_GRAPH, MPDATA_BATCH_TUNE = 1, 2
 
+# The batched kernel variants by index (include/mpdata.h, MPDATA_BATCH_TUNE):
+# (row lanes, threads per workgroup, workgroups per CU, donor-cell pass).
+BATCH_VARIANTS_F32 = [(32, 768, 1, "folded"), (32, 768, 2, "folded"), (64, 768, 1, "folded"),
+                      (64, 768, 2, "folded"), (16, 768, 1, "folded"), (16, 768, 2, "folded"),
+                      (32, 768, 1, "separate"), (32, 768, 2, "separate"), (64, 768, 1, "separate"),
+                      (64, 768, 2, "separate"), (16, 768, 1, "separate"), (16, 768, 2, "separate"),
+                      (32, 1024, 1, "folded"), (64, 1024, 1, "folded"), (16, 1024, 1, "folded"),
+                      (32, 1024, 1, "separate"), (64, 1024, 1, "separate"), (16, 1024, 1, "separate")]
+BATCH_VARIANTS_F64 = [(64, 768, 1, "folded"), (64, 768, 1, "separate")]
+
 
 class BatchItem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),

@@ -150,6 +150,15 @@ VARIANTS_F32 = [(32, 768, 1, "fold"), (32, 768, 2, "fold"), (64, 768, 1, "fold")
                 (32, 1024, 1, "split"), (64, 1024, 1, "split"), (16, 1024, 1, "split")]
 
 
+def test_variant_table_matches_binding():
+    """The binding's table of variants (which bench.py reports the tuner's
+    choice from) lists the same variants in the same order."""
+    import paper_1908_06094_amd as mp
+
+    names = {"fold": "folded", "split": "separate"}
+    assert mp.BATCH_VARIANTS_F32 == [(l, t, w, names[f]) for l, t, w, f in VARIANTS_F32]
+
+
 @pytest.mark.parametrize("variant", range(len(VARIANTS_F32)))
 @pytest.mark.parametrize("iters", [2, 3])
 def test_every_f32_variant_matches_oracle_and_single_path(variant, iters, monkeypatch):
